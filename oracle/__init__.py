@@ -1,0 +1,184 @@
+"""CPU oracle of the explicit asymptotic integrator (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It never imports the product package and the product
+never imports it; the two share only the seeded input arrays.
+
+The integrator itself is plain C (oracle.c), compiled with gcc and loaded here
+through ctypes; `build()` compiles it.  The MLP reference of the learned
+controller lives in `oracle.mlp` (numpy, FP64).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ZONE_OK, ZONE_MAX_STEPS, ZONE_DT_UNDERFLOW, ZONE_NONFINITE, ZONE_BAD_INPUT = range(5)
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("kappa", C.c_double),
+        ("tol", C.c_double),
+        ("y_floor", C.c_double),
+        ("grow_max", C.c_double),
+        ("safety", C.c_double),
+        ("shrink_min", C.c_double),
+        ("dt_min", C.c_double),
+        ("max_steps", C.c_int64),
+    ]
+
+
+def options(**kw) -> Options:
+    """Controller settings; defaults are the readings of the unspecified controller."""
+    d = dict(kappa=1.0, tol=0.01, y_floor=1e-10, grow_max=2.0, safety=0.9,
+             shrink_min=0.1, dt_min=1e-20, max_steps=10_000_000)
+    d.update(kw)
+    return Options(**d)
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-fopenmp", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.orc_rates_arrhenius.argtypes = [C.c_int32, P, P, C.c_double, P]
+        L.orc_rhs.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P]
+        L.orc_update.argtypes = [C.c_int32, P, P, P, C.c_double, C.c_double, P, P]
+        L.orc_change.argtypes = [C.c_int32, P, P, C.c_double]
+        L.orc_change.restype = C.c_double
+        L.orc_integrate_zone.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_double, P,
+                                         C.POINTER(Options), P, P, P]
+        L.orc_integrate_zone.restype = C.c_int32
+        L.orc_integrate_batch.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_int32, P, P, P,
+                                          P, P, P, P, P, C.POINTER(Options), C.c_int32]
+        L.orc_max_threads.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _Trace(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("count", C.c_int64), ("h", C.c_void_p),
+                ("r", C.c_void_p), ("accepted", C.c_void_p)]
+
+
+def rates_arrhenius(A, E, T) -> np.ndarray:
+    A, E = _f64(A), _f64(E)
+    k = np.empty_like(A)
+    lib().orc_rates_arrhenius(len(A), _p(A), _p(E), float(T), _p(k))
+    return k
+
+
+def rhs(net, k, Y):
+    """(F+, k_depletion) of Eq. eq1.1 at state Y."""
+    a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
+    k, Y = _f64(k), _f64(Y)
+    n = net.n_species
+    Fp, kd = np.empty(n), np.empty(n)
+    lib().orc_rhs(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), _p(Fp), _p(kd))
+    return Fp, kd
+
+
+def update(Y, Fp, kd, h, kappa=1.0):
+    """(Yn, branch) of one kappa-switched step; branch 1 = asymptotic form."""
+    Y, Fp, kd = _f64(Y), _f64(Fp), _f64(kd)
+    Yn = np.empty_like(Y)
+    br = np.empty(len(Y), dtype=np.int32)
+    lib().orc_update(len(Y), _p(Y), _p(Fp), _p(kd), float(h), float(kappa), _p(Yn), _p(br))
+    return Yn, br
+
+
+def change(Y, Yn, y_floor=1e-10) -> float:
+    Y, Yn = _f64(Y), _f64(Yn)
+    return lib().orc_change(len(Y), _p(Y), _p(Yn), float(y_floor))
+
+
+def integrate_zone(net, k, Y0, t_end, dt0, opts: Optional[Options] = None, trace_capacity=0):
+    """Integrate one zone; returns dict(Y, dt, n_acc, n_rej, status[, trace])."""
+    opts = opts or options()
+    a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
+    k = _f64(k)
+    Y = _f64(Y0).copy()
+    dt = np.array([dt0], dtype=np.float64)
+    na = np.zeros(1, np.int64)
+    nr = np.zeros(1, np.int64)
+    tr = None
+    trp = None
+    if trace_capacity:
+        th = np.zeros(trace_capacity)
+        trr = np.zeros(trace_capacity)
+        tacc = np.zeros(trace_capacity, np.int32)
+        tr = _Trace(trace_capacity, 0, th.ctypes.data, trr.ctypes.data, tacc.ctypes.data)
+        trp = C.byref(tr)
+    st = lib().orc_integrate_zone(net.n_species, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y),
+                                  float(t_end), _p(dt), C.byref(opts), _p(na), _p(nr), trp)
+    out = dict(Y=Y, dt=float(dt[0]), n_acc=int(na[0]), n_rej=int(nr[0]), status=int(st))
+    if tr is not None:
+        n = min(tr.count, trace_capacity)
+        out["trace"] = dict(h=th[:n].copy(), r=trr[:n].copy(), accepted=tacc[:n].astype(bool),
+                            count=int(tr.count))
+    return out
+
+
+def integrate_batch(net, zones, opts: Optional[Options] = None, n_threads: int = 0):
+    """Integrate every zone of a workloads.Zones batch; returns dict of arrays."""
+    opts = opts or options()
+    a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
+    Z, n = zones.Y0.shape
+    Y = _f64(zones.Y0).copy()
+    dt = _f64(zones.dt0).copy()
+    t_end = _f64(zones.t_end)
+    na = np.zeros(Z, np.int64)
+    nr = np.zeros(Z, np.int64)
+    st = np.zeros(Z, np.int32)
+    T = None if zones.T is None else _f64(zones.T)
+    kz = None if zones.k is None else _f64(zones.k)
+    A = None if net.A is None else _f64(net.A)
+    E = None if net.E is None else _f64(net.E)
+    if (T is None) == (kz is None):
+        raise ValueError("zones need exactly one of T and k")
+    if T is not None and (A is None or E is None):
+        raise ValueError("Arrhenius zones need a network with A and E")
+    lib().orc_integrate_batch(n, len(a), _p(a), _p(b), _p(c), _p(A), _p(E), Z, _p(Y), _p(T),
+                              _p(kz), _p(t_end), _p(dt), _p(na), _p(nr), _p(st),
+                              C.byref(opts), int(n_threads))
+    return dict(Y=Y, dt=dt, n_acc=na, n_rej=nr, status=st)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())

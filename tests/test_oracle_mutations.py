@@ -1,0 +1,55 @@
+"""Plant plausible mistakes in a copy of the oracle and check that a pin fails.
+
+Each mutation edits one line of oracle.c in a temporary copy, rebuilds it
+with gcc and runs the pin suite against the copy.  A mutation that every pin
+lets through would show a hole in the pinning of the oracle.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = {
+    "drop_one_body_creation": ("        Fp[c[j]] += f;", "        if (b[j] >= 0) Fp[c[j]] += f;"),
+    "wrong_partner_index_a": ("            kd[a[j]] += k[j] * Y[b[j]];",
+                              "            kd[a[j]] += k[j] * Y[a[j]];"),
+    "wrong_partner_index_b": ("            kd[b[j]] += k[j] * Y[a[j]];",
+                              "            kd[b[j]] += k[j] * Y[b[j]];"),
+    "one_body_rate_times_Y": ("            kd[a[j]] += k[j];\n", "            kd[a[j]] += k[j] * Y[a[j]];\n"),
+    "kappa_tie_to_euler": ("        if (kh < kappa) {", "        if (kh <= kappa) {"),
+    "euler_sign": ("Yn[i] = Y[i] + h * (Fp[i] - kd[i] * Y[i]);",
+                   "Yn[i] = Y[i] + h * (Fp[i] + kd[i] * Y[i]);"),
+    "asymptotic_denominator": ("Yn[i] = (Y[i] + h * Fp[i]) / (1.0 + kh);",
+                               "Yn[i] = (Y[i] + h * Fp[i]) / (1.0 + kd[i]);"),
+    "growth_cap_ignored": ("fmin(o->grow_max, o->safety * o->tol / r)",
+                           "fmax(o->grow_max, o->safety * o->tol / r)"),
+    "clipped_step_sets_dt": ("            if (!clipped) {", "            if (1) {"),
+    "shrink_floor_ignored": ("fmax(o->shrink_min, o->safety * o->tol / r)",
+                             "fmin(o->shrink_min, o->safety * o->tol / r)"),
+    "change_against_new_state": ("fabs(Yn[i] - Y[i]) / fmax(Y[i], y_floor)",
+                                 "fabs(Yn[i] - Y[i]) / fmax(Yn[i], y_floor)"),
+    "accept_threshold": ("int accept = r <= o->tol;", "int accept = r < 0.5 * o->tol;"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name, tmp_path):
+    before, after = MUTATIONS[name]
+    dst = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), dst,
+                    ignore=shutil.ignore_patterns("*.so", "*.tmp", "__pycache__"))
+    src = (dst / "oracle.c").read_text()
+    assert src.count(before) == 1, "mutation site not found: the oracle changed"
+    (dst / "oracle.c").write_text(src.replace(before, after))
+    env = dict(os.environ, PYTHONPATH=f"{tmp_path}{os.pathsep}{ROOT}")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         env=env, cwd=str(tmp_path), capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0, f"no pin failed for mutation {name}:\n{res.stdout[-2000:]}"
+    # and the copy really was the one under test
+    assert (dst / "liboracle.so").exists()

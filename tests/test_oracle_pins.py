@@ -1,0 +1,406 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check uses a closed form,
+an invariant of Eq. (eq1.1), an independently built dense stoichiometry, a
+library routine (scipy expm / Radau) or a hand-derived controller trace.
+Together they make a plausible mistake in the oracle fail: a dropped flux or
+a wrong reactant index breaks the invariant and the dense product, a swapped
+Euler/asymptotic branch or a wrong sign breaks the one-step closed forms, a
+wrong growth/shrink/clipping rule breaks the hand trace.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.linalg
+
+import oracle
+from paper_1409_5826_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def net_from(reactions, weight):
+    """Network from a list of (a, b or -1, c)."""
+    r = np.array(reactions, dtype=np.int32).reshape(-1, 3)
+    return workloads.Network(n_species=len(weight), reactant0=r[:, 0].copy(),
+                             reactant1=r[:, 1].copy(), product=r[:, 2].copy(),
+                             weight=np.array(weight, dtype=np.int32))
+
+
+def dense_incidence(net):
+    """Production P and destruction D matrices (N x R), built from the lists alone."""
+    n, R = net.n_species, net.n_reactions
+    P = np.zeros((n, R))
+    D = np.zeros((n, R))
+    for j in range(R):
+        P[net.product[j], j] += 1.0
+        D[net.reactant0[j], j] += 1.0
+        if net.reactant1[j] >= 0:
+            D[net.reactant1[j], j] += 1.0
+    return P, D
+
+
+def mass_action(net, k, Y):
+    """Reaction fluxes by the law of mass action: k_j times the product of its reactants."""
+    f = k * Y[net.reactant0]
+    two = net.reactant1 >= 0
+    f[two] = f[two] * Y[net.reactant1[two]]
+    return f
+
+
+def random_state(net, rng, lo=-6.0, hi=6.0):
+    k = 10.0 ** rng.uniform(lo, hi, net.n_reactions)
+    Y = rng.dirichlet(np.ones(net.n_species)) / net.weight
+    return k, Y
+
+
+ALL_NETS = ["n16_r48_const", "n150_r1604_const", "n150_r1604_arrhenius", "n365_r4400_arrhenius"]
+
+
+# --- P1: weight conservation of the right-hand side --------------------------------------------
+
+@pytest.mark.parametrize("name", ALL_NETS)
+def test_rhs_conserves_weight(name):
+    """sum_i w_i (F+_i - k_i Y_i) = 0: every reaction conserves weight (Eq. 5.35, Eq. eq1.1)."""
+    net = workloads.preset(name, n_zones=1).network
+    rng = np.random.default_rng(11)
+    w = net.weight.astype(np.float64)
+    for _ in range(5):
+        k, Y = random_state(net, rng)
+        Fp, kd = oracle.rhs(net, k, Y)
+        scale = np.sum(w * Fp)
+        assert scale > 0
+        assert abs(np.sum(w * (Fp - kd * Y))) <= 1e-12 * scale
+
+
+# --- P2: dense stoichiometry ---------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ALL_NETS)
+def test_rhs_matches_dense_stoichiometry(name):
+    """F+ = P f and k*Y = D f with mass-action fluxes f and dense incidence built independently."""
+    net = workloads.preset(name, n_zones=1).network
+    P, D = dense_incidence(net)
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        k, Y = random_state(net, rng)
+        f = mass_action(net, k, Y)
+        Fp, kd = oracle.rhs(net, k, Y)
+        np.testing.assert_allclose(Fp, P @ f, rtol=1e-13, atol=0)
+        np.testing.assert_allclose(kd * Y, D @ f, rtol=1e-13, atol=0)
+        # one-body depletion rates do not depend on Y at all
+        Y0 = Y.copy()
+        Y0[:] = 0.0
+        _, kd0 = oracle.rhs(net, k, Y0)
+        one = net.reactant1 < 0
+        expect = np.zeros(net.n_species)
+        np.add.at(expect, net.reactant0[one], k[one])
+        np.testing.assert_allclose(kd0, expect, rtol=1e-14, atol=0)
+
+
+# --- P3: A -> B, one step and full runs ----------------------------------------------------------
+
+DECAY = net_from([(0, -1, 1)], [1, 1])
+
+
+def test_one_step_closed_forms_decay():
+    """Euler gives (1 - k h) Y; the asymptotic form (k h >= kappa) gives Y / (1 + k h)."""
+    Y = np.array([0.7, 0.2])
+    for k, h, asym in [(2.0, 0.1, False), (2.0, 0.5, True), (50.0, 1.0, True), (4.0, 0.25, True)]:
+        Fp, kd = oracle.rhs(DECAY, np.array([k]), Y)
+        assert Fp[0] == 0.0 and kd[0] == k and Fp[1] == k * Y[0] and kd[1] == 0.0
+        Yn, br = oracle.update(Y, Fp, kd, h)
+        assert br[0] == int(asym) and br[1] == 0
+        want = Y[0] / (1 + k * h) if asym else (1 - k * h) * Y[0]
+        assert Yn[0] == pytest.approx(want, rel=1e-15)
+        assert Yn[1] == pytest.approx(Y[1] + h * k * Y[0], rel=1e-15)
+
+
+def test_kappa_tie_goes_to_asymptotic():
+    """k h == kappa exactly takes the asymptotic form (the paper's 'k dt >= kappa')."""
+    Y = np.array([1.0, 0.0])
+    Fp, kd = oracle.rhs(DECAY, np.array([4.0]), Y)
+    Yn, br = oracle.update(Y, Fp, kd, 0.25)   # 4 * 0.25 == 1.0 exactly
+    assert br[0] == 1 and Yn[0] == 0.5
+    Yn, br = oracle.update(Y, Fp, kd, 0.25, kappa=1.0 + 2**-52)
+    assert br[0] == 0 and Yn[0] == 0.0
+
+
+def _decay_error(tol, k=10.0, t_end=1.0):
+    out = oracle.integrate_zone(DECAY, np.array([k]), np.array([1.0, 0.0]), t_end, 1e-6,
+                                oracle.options(tol=tol))
+    assert out["status"] == oracle.ZONE_OK
+    return abs(out["Y"][0] - math.exp(-k * t_end)) / math.exp(-k * t_end), out
+
+
+def test_decay_converges_first_order():
+    """Full runs approach exp(-k t) with error shrinking about linearly in tol (first order)."""
+    errs = [_decay_error(tol)[0] for tol in (1e-2, 1e-3, 1e-4)]
+    assert errs[0] < 0.2
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 4.0 < e0 / e1 < 25.0, errs
+
+
+# --- P4: A <=> B -----------------------------------------------------------------------------
+
+EQUIL = net_from([(0, -1, 1), (1, -1, 0)], [1, 1])
+
+
+def test_equilibrium_is_a_fixed_point():
+    k1, k2 = 3.0e4, 1.0e3
+    Y = np.array([k2, k1]) / (k1 + k2)      # k1 Y_A == k2 Y_B
+    Fp, kd = oracle.rhs(EQUIL, np.array([k1, k2]), Y)
+    for h in (1e-6, 1e-3, 10.0):
+        Yn, _ = oracle.update(Y, Fp, kd, h)
+        np.testing.assert_allclose(Yn, Y, rtol=4e-16, atol=0)
+
+
+def test_two_state_relaxation():
+    """Y_A(t) = Y_eq + (Y_A0 - Y_eq) exp(-(k1+k2) t) at first order in tol.
+
+    Long runs settle at Y_A/Y_B = k2/k1 only to O(tol): with both species in
+    the asymptotic form and k h >> 1 the update maps a ratio error eps to about
+    -eps, so the controller holds an oscillation of the size it tolerates.
+    This is the behaviour near equilibrium that the paper says needs its
+    partial-equilibrium supplement (section "Future Work", item 1).
+    """
+    k1, k2 = 5.0, 2.0
+    y_eq = k2 / (k1 + k2)
+    exact = y_eq + (1.0 - y_eq) * math.exp(-(k1 + k2) * 0.5)
+    errs = []
+    for tol in (1e-3, 1e-4, 1e-5):
+        out = oracle.integrate_zone(EQUIL, np.array([k1, k2]), np.array([1.0, 0.0]), 0.5, 1e-6,
+                                    oracle.options(tol=tol))
+        errs.append(abs(out["Y"][0] - exact) / exact)
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 4.0 < e0 / e1 < 25.0, errs
+    out = oracle.integrate_zone(EQUIL, np.array([k1, k2]), np.array([1.0, 0.0]), 100.0, 1e-6,
+                                oracle.options(tol=1e-3))
+    assert out["Y"][0] / out["Y"][1] == pytest.approx(k2 / k1, rel=1e-3)
+
+
+# --- P5: Euler-only runs conserve weight; linear Euler is a product of (I + h A) -----------------
+
+def test_euler_only_conserves_weight():
+    wl = workloads.preset("n16_r48_const", n_zones=1)
+    net = wl.network
+    k = wl.zones.k[0]
+    Y0 = wl.zones.Y0[0]
+    w = net.weight.astype(np.float64)
+    out = oracle.integrate_zone(net, k, Y0, 1e-5, 1e-12,
+                                oracle.options(kappa=math.inf, max_steps=1000))
+    assert out["n_acc"] > 20
+    total0 = np.sum(w * Y0)
+    assert abs(np.sum(w * out["Y"]) - total0) <= 1e-12 * total0
+
+
+def linear_network():
+    # one-body only: an isobar group of four species with a cycle and a branch
+    return net_from([(0, -1, 1), (1, -1, 2), (2, -1, 0), (0, -1, 3), (3, -1, 1)], [1, 1, 1, 1])
+
+
+def rate_matrix(net, k):
+    n = net.n_species
+    A = np.zeros((n, n))
+    for j in range(net.n_reactions):
+        a, c = net.reactant0[j], net.product[j]
+        A[a, a] -= k[j]
+        A[c, a] += k[j]
+    return A
+
+
+def test_linear_euler_is_matrix_product():
+    net = linear_network()
+    k = np.array([3.0, 1.0, 0.5, 2.0, 0.1])
+    Y0 = np.array([0.4, 0.3, 0.2, 0.1])
+    out = oracle.integrate_zone(net, k, Y0, 0.3, 1e-3, oracle.options(kappa=math.inf, tol=1e-3),
+                                trace_capacity=100000)
+    tr = out["trace"]
+    A = rate_matrix(net, k)
+    Y = Y0.copy()
+    for h, acc in zip(tr["h"], tr["accepted"]):
+        if acc:
+            Y = (np.eye(4) + h * A) @ Y
+    np.testing.assert_allclose(out["Y"], Y, rtol=1e-12, atol=0)
+
+
+# --- P6: linear network against expm --------------------------------------------------------------
+
+def test_linear_network_against_expm():
+    net = linear_network()
+    k = np.array([3.0e3, 1.0, 0.5, 2.0e2, 0.1])
+    Y0 = np.array([0.4, 0.3, 0.2, 0.1])
+    t_end = 2.0
+    exact = scipy.linalg.expm(rate_matrix(net, k) * t_end) @ Y0
+    errs = []
+    for tol in (1e-3, 1e-4, 1e-5):
+        out = oracle.integrate_zone(net, k, Y0, t_end, 1e-8, oracle.options(tol=tol))
+        assert out["status"] == oracle.ZONE_OK
+        errs.append(np.max(np.abs(out["Y"] - exact) / exact))
+    assert errs[0] < 0.05
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.0 < e0 / e1 < 30.0, errs
+
+
+# --- P7: nonlinear tiny networks against backward Euler brute force and Radau -------------------
+
+TINY = net_from([(0, 1, 2), (2, -1, 3), (3, -1, 2), (0, 2, 4), (1, -1, 0), (4, -1, 3)],
+                [1, 1, 2, 2, 3])
+
+
+def tiny_rhs(k):
+    def f(t, y):
+        flux = mass_action(TINY, k, y)
+        P, D = dense_incidence(TINY)
+        return P @ flux - D @ flux
+    return f
+
+
+def backward_euler(k, y0, t_end, n_steps):
+    """Fixed-step backward Euler with a dense Newton solve per step (brute force)."""
+    P, D = dense_incidence(TINY)
+    S = P - D
+    h = t_end / n_steps
+    y = y0.copy()
+    n = len(y)
+    for _ in range(n_steps):
+        z = y.copy()
+        for _ in range(50):
+            flux = mass_action(TINY, k, z)
+            g = z - y - h * (S @ flux)
+            J = np.zeros((len(flux), n))   # d flux_j / d z_i
+            for j in range(len(flux)):
+                a, b = TINY.reactant0[j], TINY.reactant1[j]
+                if b < 0:
+                    J[j, a] = k[j]
+                else:
+                    J[j, a] = k[j] * z[b]
+                    J[j, b] = k[j] * z[a]
+            dz = np.linalg.solve(np.eye(n) - h * (S @ J), -g)
+            z = z + dz
+            if np.max(np.abs(dz)) <= 1e-15 * np.max(np.abs(z)):
+                break
+        y = z
+    return y
+
+
+def test_tiny_nonlinear_against_brute_force():
+    k = np.array([40.0, 5.0, 1.0, 8.0, 0.3, 2.0])
+    y0 = np.array([0.3, 0.3, 0.1, 0.05, 0.05])
+    t_end = 1.0
+    sol = scipy.integrate.solve_ivp(tiny_rhs(k), (0, t_end), y0, method="Radau", rtol=1e-12,
+                                    atol=1e-16)
+    ref = sol.y[:, -1]
+    be = backward_euler(k, y0, t_end, 20000)
+    # brute-force backward Euler at tiny step agrees with Radau to first order in its step
+    assert np.max(np.abs(be - ref) / ref) < 1e-3
+    errs = []
+    for tol in (1e-3, 1e-4, 1e-5):
+        out = oracle.integrate_zone(TINY, k, y0, t_end, 1e-6, oracle.options(tol=tol))
+        assert out["status"] == oracle.ZONE_OK
+        errs.append(np.max(np.abs(out["Y"] - ref) / ref))
+        # and sits within O(tol) of the brute-force solution
+        assert np.max(np.abs(out["Y"] - be) / be) < 30 * tol + 1e-3
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.0 < e0 / e1 < 30.0, errs
+
+
+# --- P8: hand-traced controller ----------------------------------------------------------------
+
+def load_trace_cases():
+    with open(os.path.join(GOLDEN, "controller_trace.json")) as fh:
+        return json.load(fh)["cases"]
+
+
+@pytest.mark.parametrize("case", load_trace_cases(), ids=lambda c: c["name"])
+def test_controller_hand_trace(case):
+    k = case["k"]
+    out = oracle.integrate_zone(DECAY, np.array([k]), np.array([1.0, 1.0]), case["t_end"],
+                                case["dt0"], oracle.options(), trace_capacity=10000)
+    tr = out["trace"]
+    want_h = np.concatenate([[h] * n for h, _, n in case["attempts"]])
+    want_acc = np.concatenate([[acc] * n for _, acc, n in case["attempts"]])
+    assert tr["count"] == len(want_h)
+    np.testing.assert_array_equal(tr["accepted"], want_acc)
+    np.testing.assert_allclose(tr["h"], want_h, rtol=1e-12, atol=1e-12 * case["t_end"])
+    assert out["n_acc"] == case["n_acc"] and out["n_rej"] == case["n_rej"]
+    assert out["dt"] == pytest.approx(case["dt_out"], rel=1e-12)
+    ya = np.prod([(1.0 - k * h) ** n for h, acc, n in case["attempts"] if acc])
+    assert out["Y"][0] == pytest.approx(ya, rel=1e-12)
+    assert out["Y"][1] == pytest.approx(2.0 - ya, rel=1e-12)
+
+
+# --- P9: the asymptotic drift is accounted for exactly -------------------------------------------
+
+@pytest.mark.parametrize("name", ["n16_r48_const", "n150_r1604_const"])
+def test_weight_drift_identity(name):
+    """sum w (Yn - Y) = -sum_{asymptotic i} w h^2 k_i (F+_i - k_i Y_i) / (1 + k_i h)."""
+    net = workloads.preset(name, n_zones=1).network
+    w = net.weight.astype(np.float64)
+    rng = np.random.default_rng(9)
+    mixed = 0
+    for h in (1e-8, 1e-6, 1e-4, 1e-2):
+        k, Y = random_state(net, rng, -2.0, 8.0)
+        Fp, kd = oracle.rhs(net, k, Y)
+        Yn, br = oracle.update(Y, Fp, kd, h)
+        asy = br == 1
+        mixed += bool(asy.any() and (~asy).any())
+        rhs_ = -np.sum((w * h * h * kd * (Fp - kd * Y) / (1 + kd * h))[asy])
+        # rounding floor: the identity cancels terms as large as h * sum w (F+ + k Y)
+        scale = np.sum(w * Y) + h * np.sum(w * (Fp + kd * Y))
+        assert abs(np.sum(w * (Yn - Y)) - rhs_) <= 1e-13 * scale
+    assert mixed >= 2
+
+
+# --- P10: steady states are fixed points of both branches --------------------------------------
+
+def test_steady_cycle_is_fixed_point():
+    cyc = net_from([(0, -1, 1), (1, -1, 2), (2, -1, 0)], [1, 1, 1])
+    k = np.full(3, 7.0)
+    Y = np.full(3, 1.0 / 3.0)
+    Fp, kd = oracle.rhs(cyc, k, Y)
+    for h in (1e-3, 0.5, 100.0):   # Euler, asymptotic, deep asymptotic
+        Yn, _ = oracle.update(Y, Fp, kd, h)
+        np.testing.assert_allclose(Yn, Y, rtol=4e-16, atol=0)
+
+
+# --- P11: positivity, P12: determinism, statuses -------------------------------------------------
+
+def test_positivity_and_thread_invariance():
+    wl = workloads.preset("n150_r1604_const", n_zones=8)
+    one = oracle.integrate_batch(wl.network, wl.zones, n_threads=1)
+    many = oracle.integrate_batch(wl.network, wl.zones, n_threads=4)
+    assert (one["status"] == oracle.ZONE_OK).all()
+    assert (one["Y"] >= 0).all()
+    for key in ("Y", "dt", "n_acc", "n_rej", "status"):
+        np.testing.assert_array_equal(one[key], many[key])
+
+
+def test_arrhenius_rates():
+    A = np.array([1e3, 2.5e11, 7.0])
+    E = np.array([0.0, 40.0, 3.5])
+    k = oracle.rates_arrhenius(A, E, 2.0)
+    np.testing.assert_allclose(k, A * np.exp(-E / 2.0), rtol=2e-16)
+    assert k[0] == 1e3
+
+
+def test_zone_statuses():
+    wl = workloads.preset("n16_r48_const", n_zones=1)
+    net, k, Y0 = wl.network, wl.zones.k[0], wl.zones.Y0[0]
+    out = oracle.integrate_zone(net, k, Y0, 1e-2, 1e-12, oracle.options(max_steps=10))
+    assert out["status"] == oracle.ZONE_MAX_STEPS and out["n_acc"] + out["n_rej"] == 10
+    out = oracle.integrate_zone(net, k, Y0, 1e-2, 1e-2, oracle.options(dt_min=1e-4))
+    assert out["status"] == oracle.ZONE_DT_UNDERFLOW and out["dt"] < 1e-4
+    np.testing.assert_array_equal(out["Y"], Y0)   # no step was accepted
+    bad = Y0.copy()
+    bad[3] = np.nan
+    out = oracle.integrate_zone(net, k, bad, 1e-2, 1e-12)
+    assert out["status"] == oracle.ZONE_NONFINITE and out["n_acc"] == 0
+    bad[3] = -1.0
+    out = oracle.integrate_zone(net, k, bad, 1e-2, 1e-12)
+    assert out["status"] == oracle.ZONE_BAD_INPUT
+    out = oracle.integrate_zone(net, k, Y0, 0.0, 1e-12)
+    assert out["status"] == oracle.ZONE_OK and out["n_acc"] == 0 and out["dt"] == 1e-12
