@@ -1,0 +1,176 @@
+"""Benchmark of the batched explicit asymptotic integrator on one MI355X.
+
+One step = one asy_integrate_batch call that integrates every zone of the
+workload from t = 0 to t_end (rates, fluxes, creation/depletion sums,
+kappa-switched updates and step control), starting from the same initial
+state each time.  Inputs are resident in HBM before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  value = accepted zone-steps per second over the K
+timed steps.  roofline: the integrator is bound by LDS traffic; achieved =
+algorithmic LDS bytes per attempted zone-step x attempted zone-steps per
+launch / average launch time (HIP events on the launch stream).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs at 2.4 GHz; an LDS delivers 128 bytes per clock per CU.
+N_CU = 256
+CLOCK_HZ = 2.4e9
+LDS_BYTES_PER_CLK_CU = 128
+LDS_PEAK_GBS = N_CU * LDS_BYTES_PER_CLK_CU * CLOCK_HZ / 1e9
+
+
+def algorithmic_bytes_per_zone_step(n_species: int, n_reactions: int, n_destruction: int) -> int:
+    """LDS bytes one attempted step of one zone must move (FP64 = 8 B, index = 2 B).
+
+    Per reaction: read k_j, write the flux, read it back with its product
+    index (26 B).  Per destruction incidence: gather the partner abundance
+    with its index, write the partial rate, read it back (26 B).  Per
+    species: five reads/writes of Y, F+, k, Yn (40 B).
+    """
+    return 26 * (n_reactions + n_destruction) + 40 * n_species
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n150_r1604_arrhenius")
+    ap.add_argument("--zones", type=int, default=None)
+    ap.add_argument("--cpu-sample-stride", type=int, default=16,
+                    help="oracle baseline integrates every Nth zone")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default=None, help="JSON dict of asy_launch fields")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(zones shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1409_5826_amd import binding, workloads
+
+    torch.cuda.set_device(0)
+    wl = workloads.preset(args.workload, n_zones=args.zones)
+    net = binding.Network(wl.network)
+    if args.launch:
+        net.set_launch(**json.loads(args.launch))
+    buf = net.zone_buffers(wl.zones)
+    Y0 = buf["Y"].clone()
+    dt0 = buf["dt"].clone()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        buf["Y"].copy_(Y0)
+        buf["dt"].copy_(dt0)
+        net.integrate(buf, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        buf["Y"].copy_(Y0)
+        buf["dt"].copy_(dt0)
+        starts[i].record(stream)
+        net.integrate(buf, stream=stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+
+    n_acc = buf["n_accepted"].cpu().numpy()
+    n_rej = buf["n_rejected"].cpu().numpy()
+    status = buf["zone_status"].cpu().numpy()
+    if not (status == binding.ZONE_OK).all():
+        print(f"warning: {int((status != 0).sum())} zones did not reach t_end", file=sys.stderr)
+    acc_per_step = int(n_acc.sum())
+    att_per_step = int(n_acc.sum() + n_rej.sum())
+    value = acc_per_step * args.steps / elapsed
+    n = wl.network
+    b_step = algorithmic_bytes_per_zone_step(n.n_species, n.n_reactions, n.n_destruction)
+    avg_launch_s = float(np.mean(launch_ms)) / 1e3
+    achieved = b_step * att_per_step / avg_launch_s / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        idx = np.arange(0, wl.zones.n_zones, args.cpu_sample_stride)
+        sub = wl.zones.subset(idx)
+        threads = oracle.max_threads()
+        tc = time.perf_counter()
+        ref = oracle.integrate_batch(n, sub, n_threads=threads)
+        tcpu = time.perf_counter() - tc
+        cpu = {
+            "value": float(ref["n_acc"].sum() / tcpu),
+            "unit": "zone-steps/s",
+            "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{len(idx)} of {wl.zones.n_zones} zones (every {args.cpu_sample_stride}th), "
+                      f"{int(ref['n_acc'].sum())} accepted zone-steps in {tcpu:.2f} s",
+        }
+
+    out = {
+        "metric": "zone-steps/sec and time-to-t_end for 4096 zones",
+        "value": value,
+        "unit": "zone-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "description": wl.description,
+            "zones": wl.zones.n_zones,
+            "n_species": n.n_species,
+            "n_reactions": n.n_reactions,
+            "tol": wl.tol,
+            "time_to_t_end_ms": float(np.mean(launch_ms)),
+            "accepted_zone_steps": acc_per_step,
+            "rejected_zone_steps": att_per_step - acc_per_step,
+            "launch": net.get_launch(),
+            "parallelism": "1 GPU",
+        },
+        "roofline": {
+            "bound": "lds",
+            "achieved": achieved,
+            "peak": LDS_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / LDS_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_zone_step": b_step,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,210 @@
+/*
+ * asynet: batched explicit asymptotic integration of stiff kinetic networks
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the algebraically stabilized explicit integrator of Brock,
+ * Belt, Billings and Guidry, "Explicit Integration with GPU Acceleration for
+ * Large Kinetic Networks" (arXiv:1409.5826):
+ *
+ *   dY_i/dt = F+_i - F-_i = F+_i - k_i Y_i                      Eq. (eq1.1)
+ *
+ * advanced per species either by forward Euler (k_i dt < kappa) or by the
+ * asymptotic form (section "Algebraic Stabilization of Solutions Using
+ * Asymptotic Approximations", Eq. (asySophia)):
+ *
+ *   Y_i <- (Y_i + dt F+_i) / (1 + k_i dt)                        (k_i dt >= kappa)
+ *
+ * with kappa = 1 and an adaptive network timestep.  Many independent networks
+ * ("zones", one per hydrodynamic zone) share one reaction structure and are
+ * integrated together (section "Multiple Parallel Networks and Thread
+ * Occupancy").  Rates are constant over one integration because temperature
+ * and density are frozen over a hydro step (section "GPU Virtues and the
+ * Explicit Approach", footnote on rates).
+ *
+ * Conventions for every entry point:
+ *  - Arguments documented "host" are host pointers, read during the call and
+ *    owned by the caller.  Arguments documented "device" are device pointers
+ *    on the current HIP device, owned by the caller, which must keep them
+ *    valid until the work queued on the given stream has finished.
+ *  - A negative asy_status reports an API or device error; asy_last_error()
+ *    then returns a message (thread-local).  On an argument error nothing is
+ *    modified and nothing is queued.
+ *  - Per-zone numerical outcomes are written to zone_status; the call still
+ *    returns ASY_OK.
+ *  - A network handle owns device memory and a work queue.  Calls on one
+ *    handle must be ordered on one stream; use one handle per concurrent
+ *    stream.  Handles are not thread-safe.
+ */
+#ifndef ASYNET_H
+#define ASYNET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct asy_network asy_network; /* opaque; owned by the library */
+
+typedef enum {
+    ASY_OK = 0,
+    ASY_EINVAL = -1,  /* invalid argument or descriptor */
+    ASY_ENOMEM = -2,  /* device or host allocation failed */
+    ASY_EDEVICE = -3, /* HIP runtime error, or no usable gfx950 device */
+    ASY_ENOTSUP = -4, /* valid request this build does not support */
+    ASY_ESTATE = -5   /* call out of order (e.g. learned controller before asy_set_mlp) */
+} asy_status;
+
+/* Per-zone outcome. */
+enum {
+    ASY_ZONE_OK = 0,           /* reached t_end */
+    ASY_ZONE_MAX_STEPS = 1,    /* attempted-step budget exhausted before t_end */
+    ASY_ZONE_DT_UNDERFLOW = 2, /* a rejection asked for a step below dt_min */
+    ASY_ZONE_NONFINITE = 3,    /* an input of the zone (Y, rate, T, t_end, dt) is not finite */
+    ASY_ZONE_BAD_INPUT = 4     /* negative Y or rate, T <= 0, t_end < 0 or dt <= 0 */
+};
+
+/* Rate forms. */
+enum {
+    ASY_RATES_PER_ZONE = 0, /* constant k[z][j] supplied per zone and reaction */
+    ASY_RATES_ARRHENIUS = 1 /* k_j = A_j exp(-E_j / T_z), evaluated once per call */
+};
+
+/* Step-size controllers. */
+enum {
+    ASY_CTRL_PLAIN = 0,  /* dY/Y-limited rule below */
+    ASY_CTRL_LEARNED = 1 /* MLP proposal with fallback to the plain rule */
+};
+
+/*
+ * Reaction structure (section "Implementation of Realistic Kinetic Networks").
+ * Reaction j destroys reactant0[j] (and reactant1[j] for a two-body
+ * reaction; -1 marks a one-body reaction) and creates product[j], with flux
+ * f_j = k_j Y_a (Y_b).  All arrays are host arrays of length n_reactions
+ * (weight: n_species), copied during asy_network_create.
+ */
+typedef struct {
+    int32_t n_species;        /* N >= 1 */
+    int32_t n_reactions;      /* R >= 1 */
+    const int32_t *reactant0; /* [R] species index in [0, N) */
+    const int32_t *reactant1; /* [R] species index in [0, N), distinct from reactant0, or -1 */
+    const int32_t *product;   /* [R] species index, distinct from the reactants */
+    const int32_t *weight;    /* [N] conserved integer weights (mass numbers, Eq. 5.35); NULL skips the check */
+    int32_t rate_form;        /* ASY_RATES_PER_ZONE or ASY_RATES_ARRHENIUS */
+    const double *A;          /* [R] Arrhenius prefactors (> 0, finite); NULL for per-zone rates */
+    const double *E;          /* [R] activation energies in units of T (finite); NULL for per-zone rates */
+} asy_network_desc;
+
+/*
+ * Integration options.  The paper fixes kappa = 1 and leaves the timestep
+ * controller unspecified; the controller of this library is, per zone:
+ *   r = max_i |Yn_i - Y_i| / max(Y_i, y_floor)   (+inf if any Yn_i is not finite)
+ *   accept iff r <= tol;
+ *   after an accepted, unclipped step h: dt = h * min(grow_max, safety*tol/r);
+ *   after a rejection:                   dt = h * max(shrink_min, safety*tol/r),
+ *                                        and dt < dt_min ends the zone;
+ *   the last step is clipped to land on t_end and leaves dt unchanged.
+ */
+typedef struct {
+    double kappa;      /* stiffness switch; 1.0 */
+    double tol;        /* relative-change bound; 0.01 */
+    double y_floor;    /* abundance floor of the change measure; 1e-10 */
+    double grow_max;   /* 2.0 */
+    double safety;     /* 0.9 */
+    double shrink_min; /* 0.1 */
+    double dt_min;     /* 1e-20 */
+    int64_t max_steps; /* attempted steps per zone; 10,000,000 */
+    int32_t controller;/* ASY_CTRL_PLAIN */
+    int32_t reserved;  /* must be 0 */
+} asy_options;
+
+/* Launch configuration of the integrator kernel (see asy_autotune). */
+typedef struct {
+    int32_t variant;          /* kernel variant: 0 = one zone per workgroup */
+    int32_t threads_per_zone; /* threads cooperating on one zone (multiple of 64) */
+    int32_t zones_per_group;  /* zones resident in one workgroup */
+    int32_t groups_per_cu;    /* persistent workgroups launched per compute unit; 0 = one per zone */
+    int32_t use_graph;        /* 1: replay a captured hipGraph for repeated identical calls */
+    int32_t reserved;         /* must be 0 */
+} asy_launch;
+
+/* Fill *o with the defaults listed above.  o: host, non-NULL. */
+void asy_options_default(asy_options *o);
+
+/*
+ * Validate a reaction structure and upload it to the current HIP device (the
+ * paper's one-time setup copy of rate-library parameters, section
+ * "Implementing the Explicit Asymptotic Algorithm on a CPU-GPU System").
+ * Rejects with ASY_EINVAL: sizes < 1, an index out of range, reactant0 ==
+ * reactant1, a product equal to a reactant, a reaction that breaks
+ * weight conservation (when weight != NULL), a missing or extra Arrhenius
+ * array, a non-finite or non-positive A, a non-finite E.  Validation runs
+ * on the host before any device call.  *out receives the handle on success
+ * and is left untouched otherwise.
+ */
+asy_status asy_network_create(const asy_network_desc *desc, asy_network **out);
+
+/* Release a handle and its device memory after synchronizing the device.  NULL is a no-op. */
+void asy_network_destroy(asy_network *net);
+
+/*
+ * Integrate n_zones independent zones from t = 0 to t_end[z] with constant
+ * rates (one hydro step of the operator-split scheme, section
+ * "Operator-Split Integration Timesteps"; the per-zone inputs and outputs
+ * are the paper's copy-in and copy-out lists of section "Implementing the
+ * Explicit Asymptotic Algorithm on a CPU-GPU System").
+ *
+ *  Y           device [n_zones][N] FP64, row-major; in: Y(0), out: the last
+ *              accepted state (unchanged for a zone that fails its input checks)
+ *  T           device [n_zones] FP64 temperatures for ASY_RATES_ARRHENIUS, else NULL
+ *  k_zone      device [n_zones][R] FP64 rates for ASY_RATES_PER_ZONE, else NULL
+ *  t_end       device [n_zones] FP64 interval lengths (>= 0)
+ *  dt          device [n_zones] FP64; in: trial step (> 0), out: next trial step
+ *  n_accepted  device [n_zones] int64, out
+ *  n_rejected  device [n_zones] int64, out
+ *  zone_status device [n_zones] int32, out (ASY_ZONE_*)
+ *  opts        host; NULL means defaults
+ *  stream      hipStream_t to queue the work on (NULL = the null stream);
+ *              the call returns after queuing; outputs are valid once the
+ *              stream has been synchronized
+ *
+ * n_zones == 0 queues nothing and returns ASY_OK.  The arithmetic is FP64
+ * without fused multiply-add contraction, and every creation/depletion sum
+ * takes its terms in ascending reaction index, so results do not depend on
+ * the launch configuration.
+ */
+asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_t n_zones,
+                               double *Y, const double *T, const double *k_zone,
+                               const double *t_end, double *dt, int64_t *n_accepted,
+                               int64_t *n_rejected, int32_t *zone_status, void *stream);
+
+/* Current launch configuration of a handle.  cfg: host, out. */
+asy_status asy_get_launch(const asy_network *net, asy_launch *cfg);
+
+/*
+ * Set the launch configuration (validated against the device limits and the
+ * network's LDS footprint; ASY_EINVAL if it cannot run).  The results of
+ * asy_integrate_batch do not depend on it, only the speed does.
+ */
+asy_status asy_set_launch(asy_network *net, const asy_launch *cfg);
+
+/*
+ * Time candidate launch configurations on copies of the first sample_zones
+ * zones of the given batch (same arguments as asy_integrate_batch, left
+ * unmodified) and keep the fastest.  Synchronous.  best: host, out, may be NULL.
+ */
+asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sample_zones,
+                        const double *Y, const double *T, const double *k_zone,
+                        const double *t_end, const double *dt, asy_launch *best);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *asy_last_error(void);
+
+/* Library version string. */
+const char *asy_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASYNET_H */

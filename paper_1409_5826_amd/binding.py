@@ -1,0 +1,295 @@
+"""ctypes binding of the asynet C ABI (include/asynet.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+library.  torch supplies device memory and streams.  Importing this module
+does not touch the GPU; loading the library does, and it raises if the
+library has not been built (python -m paper_1409_5826_amd.build) -- there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasynet.so")
+
+ASY_OK, ASY_EINVAL, ASY_ENOMEM, ASY_EDEVICE, ASY_ENOTSUP, ASY_ESTATE = 0, -1, -2, -3, -4, -5
+ZONE_OK, ZONE_MAX_STEPS, ZONE_DT_UNDERFLOW, ZONE_NONFINITE, ZONE_BAD_INPUT = range(5)
+RATES_PER_ZONE, RATES_ARRHENIUS = 0, 1
+CTRL_PLAIN, CTRL_LEARNED = 0, 1
+
+# Every symbol include/asynet.h declares.
+EXPORTS = (
+    "asy_options_default",
+    "asy_network_create",
+    "asy_network_destroy",
+    "asy_integrate_batch",
+    "asy_get_launch",
+    "asy_set_launch",
+    "asy_autotune",
+    "asy_last_error",
+    "asy_version",
+)
+
+
+class AsyError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class asy_network_desc(C.Structure):
+    _fields_ = [
+        ("n_species", C.c_int32),
+        ("n_reactions", C.c_int32),
+        ("reactant0", C.c_void_p),
+        ("reactant1", C.c_void_p),
+        ("product", C.c_void_p),
+        ("weight", C.c_void_p),
+        ("rate_form", C.c_int32),
+        ("A", C.c_void_p),
+        ("E", C.c_void_p),
+    ]
+
+
+class asy_options(C.Structure):
+    _fields_ = [
+        ("kappa", C.c_double),
+        ("tol", C.c_double),
+        ("y_floor", C.c_double),
+        ("grow_max", C.c_double),
+        ("safety", C.c_double),
+        ("shrink_min", C.c_double),
+        ("dt_min", C.c_double),
+        ("max_steps", C.c_int64),
+        ("controller", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class asy_launch(C.Structure):
+    _fields_ = [
+        ("variant", C.c_int32),
+        ("threads_per_zone", C.c_int32),
+        ("zones_per_group", C.c_int32),
+        ("groups_per_cu", C.c_int32),
+        ("use_graph", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Load libasynet.so (raises if it is missing: there is no other path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1409_5826_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        L.asy_options_default.argtypes = [C.POINTER(asy_options)]
+        L.asy_options_default.restype = None
+        L.asy_network_create.argtypes = [C.POINTER(asy_network_desc), C.POINTER(P)]
+        L.asy_network_create.restype = I32
+        L.asy_network_destroy.argtypes = [P]
+        L.asy_network_destroy.restype = None
+        L.asy_integrate_batch.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, P, P, P, P]
+        L.asy_integrate_batch.restype = I32
+        L.asy_get_launch.argtypes = [P, C.POINTER(asy_launch)]
+        L.asy_get_launch.restype = I32
+        L.asy_set_launch.argtypes = [P, C.POINTER(asy_launch)]
+        L.asy_set_launch.restype = I32
+        L.asy_autotune.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, C.POINTER(asy_launch)]
+        L.asy_autotune.restype = I32
+        L.asy_last_error.argtypes = []
+        L.asy_last_error.restype = C.c_char_p
+        L.asy_version.argtypes = []
+        L.asy_version.restype = C.c_char_p
+        _ = I64
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().asy_last_error().decode()
+
+
+def _check(st: int, where: str):
+    if st != ASY_OK:
+        raise AsyError(st, where, last_error())
+
+
+def options_default(**overrides) -> asy_options:
+    o = asy_options()
+    lib().asy_options_default(C.byref(o))
+    for key, val in overrides.items():
+        setattr(o, key, val)
+    return o
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def asy_network_create(n_species, reactant0, reactant1, product, weight=None, A=None, E=None):
+    """Create a handle from host arrays; returns the opaque pointer (int)."""
+    r0, r1, pr = _i32(reactant0), _i32(reactant1), _i32(product)
+    w = None if weight is None else _i32(weight)
+    a = None if A is None else _f64(A)
+    e = None if E is None else _f64(E)
+    d = asy_network_desc(
+        n_species=int(n_species), n_reactions=len(r0),
+        reactant0=r0.ctypes.data, reactant1=r1.ctypes.data, product=pr.ctypes.data,
+        weight=None if w is None else w.ctypes.data,
+        rate_form=RATES_ARRHENIUS if (a is not None or e is not None) else RATES_PER_ZONE,
+        A=None if a is None else a.ctypes.data, E=None if e is None else e.ctypes.data)
+    h = C.c_void_p()
+    _check(lib().asy_network_create(C.byref(d), C.byref(h)), "asy_network_create")
+    return h.value
+
+
+def asy_network_destroy(handle):
+    lib().asy_network_destroy(handle)
+
+
+def _dev_ptr(t, dtype, shape, name):
+    import torch
+
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def asy_integrate_batch(handle, n_species, n_reactions, Y, t_end, dt, n_accepted, n_rejected,
+                        zone_status, T=None, k_zone=None, opts: Optional[asy_options] = None,
+                        stream=None):
+    """Queue the integration of Y.shape[0] zones on `stream` (default: torch's current)."""
+    import torch
+
+    Z = int(Y.shape[0])
+    args = [
+        _dev_ptr(Y, torch.float64, (Z, n_species), "Y"),
+        _dev_ptr(T, torch.float64, (Z,), "T"),
+        _dev_ptr(k_zone, torch.float64, (Z, n_reactions), "k_zone"),
+        _dev_ptr(t_end, torch.float64, (Z,), "t_end"),
+        _dev_ptr(dt, torch.float64, (Z,), "dt"),
+        _dev_ptr(n_accepted, torch.int64, (Z,), "n_accepted"),
+        _dev_ptr(n_rejected, torch.int64, (Z,), "n_rejected"),
+        _dev_ptr(zone_status, torch.int32, (Z,), "zone_status"),
+    ]
+    st = lib().asy_integrate_batch(handle, None if opts is None else C.byref(opts), Z, *args,
+                                   _stream_ptr(stream))
+    _check(st, "asy_integrate_batch")
+
+
+def asy_get_launch(handle) -> asy_launch:
+    c = asy_launch()
+    _check(lib().asy_get_launch(handle, C.byref(c)), "asy_get_launch")
+    return c
+
+
+def asy_set_launch(handle, **fields):
+    c = asy_get_launch(handle)
+    for key, val in fields.items():
+        setattr(c, key, int(val))
+    _check(lib().asy_set_launch(handle, C.byref(c)), "asy_set_launch")
+
+
+def asy_autotune(handle, n_species, n_reactions, Y, t_end, dt, T=None, k_zone=None,
+                 sample_zones=None, opts: Optional[asy_options] = None) -> asy_launch:
+    import torch
+
+    Z = int(Y.shape[0])
+    best = asy_launch()
+    st = lib().asy_autotune(
+        handle, None if opts is None else C.byref(opts), Z if sample_zones is None else int(sample_zones),
+        _dev_ptr(Y, torch.float64, (Z, n_species), "Y"), _dev_ptr(T, torch.float64, (Z,), "T"),
+        _dev_ptr(k_zone, torch.float64, (Z, n_reactions), "k_zone"),
+        _dev_ptr(t_end, torch.float64, (Z,), "t_end"), _dev_ptr(dt, torch.float64, (Z,), "dt"),
+        C.byref(best))
+    _check(st, "asy_autotune")
+    return best
+
+
+def asy_version() -> str:
+    return lib().asy_version().decode()
+
+
+class Network:
+    """Convenience owner of a handle built from a workloads.Network."""
+
+    def __init__(self, net):
+        self.n_species = int(net.n_species)
+        self.n_reactions = int(net.n_reactions)
+        self.arrhenius = net.A is not None
+        self.handle = asy_network_create(net.n_species, net.reactant0, net.reactant1, net.product,
+                                         net.weight, net.A, net.E)
+
+    def close(self):
+        if self.handle:
+            asy_network_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def zone_buffers(self, zones, device="cuda"):
+        """Device copies of a workloads.Zones batch plus output buffers."""
+        import torch
+
+        Z = zones.n_zones
+        buf = dict(
+            Y=torch.as_tensor(zones.Y0, dtype=torch.float64, device=device).contiguous(),
+            t_end=torch.as_tensor(zones.t_end, dtype=torch.float64, device=device),
+            dt=torch.as_tensor(zones.dt0, dtype=torch.float64, device=device).clone(),
+            n_accepted=torch.zeros(Z, dtype=torch.int64, device=device),
+            n_rejected=torch.zeros(Z, dtype=torch.int64, device=device),
+            zone_status=torch.full((Z,), -1, dtype=torch.int32, device=device),
+            T=None if zones.T is None else torch.as_tensor(zones.T, dtype=torch.float64, device=device),
+            k_zone=None if zones.k is None else torch.as_tensor(zones.k, dtype=torch.float64,
+                                                                  device=device).contiguous(),
+        )
+        return buf
+
+    def integrate(self, buf, opts=None, stream=None):
+        asy_integrate_batch(self.handle, self.n_species, self.n_reactions, buf["Y"], buf["t_end"],
+                            buf["dt"], buf["n_accepted"], buf["n_rejected"], buf["zone_status"],
+                            T=buf["T"], k_zone=buf["k_zone"], opts=opts, stream=stream)
+
+    def set_launch(self, **fields):
+        asy_set_launch(self.handle, **fields)
+
+    def get_launch(self) -> dict:
+        return asy_get_launch(self.handle).as_dict()

@@ -1,0 +1,284 @@
+// Device code of the batched explicit asymptotic integrator (gfx950).
+//
+// One zone is one independent network instance (its own abundances, rates,
+// interval and step).  A workgroup integrates one zone at a time, keeping the
+// zone's rates and abundances in LDS for the whole interval, and pulls the
+// next zone from a device-wide counter when it is done, so zones with uneven
+// step counts balance across the chip (the paper launches one block per
+// network and leaves load balance open, section "Multiple Parallel Networks
+// and Thread Occupancy").
+//
+// Arithmetic is FP64 and the file is compiled with -ffp-contract=off: every
+// product and sum rounds as written, and each creation/depletion sum takes its
+// terms in ascending reaction index, so a zone's result does not depend on
+// the launch configuration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace asynet {
+
+constexpr int kWave = 64;
+
+enum ZoneStatus : int32_t {
+    kZoneOk = 0,
+    kZoneMaxSteps = 1,
+    kZoneDtUnderflow = 2,
+    kZoneNonfinite = 3,
+    kZoneBadInput = 4,
+};
+
+// Species-major incidence of a network, built on the host.
+//  production row of species i:  entries [prod_ptr[i], prod_ptr[i+1]), ascending reaction
+//    index, each entry = (reaction j, reactant0[j], reactant1[j] or -1)
+//  destruction row of species i: entries [dest_ptr[i], dest_ptr[i+1]), ascending reaction
+//    index, each entry = (reaction j, the other reactant of j or -1)
+struct DevNetwork {
+    int32_t n_species;
+    int32_t n_reactions;
+    const int32_t *prod_ptr;
+    const int32_t *prod_rx;
+    const int32_t *prod_a;
+    const int32_t *prod_b;
+    const int32_t *dest_ptr;
+    const int32_t *dest_rx;
+    const int32_t *dest_o;
+    const double *A;  // Arrhenius prefactors or nullptr
+    const double *E;  // Arrhenius activation energies or nullptr
+};
+
+struct DevOptions {
+    double kappa, tol, y_floor, grow_max, safety, shrink_min, dt_min;
+    int64_t max_steps;
+};
+
+struct ZoneArgs {
+    int32_t n_zones;
+    double *Y;
+    const double *T;
+    const double *k_zone;
+    const double *t_end;
+    double *dt;
+    int64_t *n_acc;
+    int64_t *n_rej;
+    int32_t *status;
+    int32_t *queue;  // zone counter, zero at launch
+};
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ inline int wave_or(int v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v |= __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__global__ void reset_queue_kernel(int32_t *queue)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        queue[0] = 0;
+}
+
+// Variant 0: one zone per workgroup, species strided over the workgroup's
+// threads.  Dynamic LDS: k[R], Y[N], Yn[N] (FP64).
+template <int NTHREADS, bool ARRHENIUS>
+__global__ void __launch_bounds__(NTHREADS)
+integrate_group_kernel(DevNetwork net, DevOptions o, ZoneArgs za)
+{
+    constexpr int NWAVES = NTHREADS / kWave;
+    extern __shared__ double lds[];
+    __shared__ double wave_r[NWAVES];
+    __shared__ int wave_flag[NWAVES];
+    __shared__ int zone_slot;
+
+    const int N = net.n_species;
+    const int R = net.n_reactions;
+    double *k = lds;
+    double *Y = k + R;
+    double *Yn = Y + N;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = tid % kWave;
+
+    for (;;) {
+        // Fetch the next zone.  Wave 0 takes a ticket with a wave-wide atomic
+        // (lane 0 adds 1, the others 0) and broadcasts lane 0's ticket with a
+        // cross-lane read, so every lane leaves this block with the same z and
+        // no lane-divergent branch sits at the head of the loop.
+        if (wave == 0) {
+            int ticket = atomicAdd(za.queue, lane == 0 ? 1 : 0);
+            ticket = __shfl(ticket, 0, kWave);
+            if (lane == 0)
+                zone_slot = ticket;
+        }
+        __syncthreads();
+        const int z = __builtin_amdgcn_readfirstlane(zone_slot);
+        __syncthreads();
+        if (z >= za.n_zones)
+            break;
+
+        // ---- load the zone: rates (evaluated once per interval), abundances, checks
+        const double t_end = za.t_end[z];
+        const double dt0 = za.dt[z];
+        int flag = 0;  // bit 0: non-finite input, bit 1: out-of-domain input
+        if (ARRHENIUS) {
+            const double T = za.T[z];
+            if (!isfinite(T))
+                flag |= 1;
+            else if (!(T > 0.0))
+                flag |= 2;
+            for (int j = tid; j < R; j += NTHREADS) {
+                double kj = net.A[j] * exp(-net.E[j] / T);
+                k[j] = kj;
+                if (!isfinite(kj))
+                    flag |= 1;
+            }
+        } else {
+            const double *kz = za.k_zone + (size_t)z * R;
+            for (int j = tid; j < R; j += NTHREADS) {
+                double kj = kz[j];
+                k[j] = kj;
+                if (!isfinite(kj))
+                    flag |= 1;
+                else if (kj < 0.0)
+                    flag |= 2;
+            }
+        }
+        const double *Yz = za.Y + (size_t)z * N;
+        for (int i = tid; i < N; i += NTHREADS) {
+            double y = Yz[i];
+            Y[i] = y;
+            if (!isfinite(y))
+                flag |= 1;
+            else if (y < 0.0)
+                flag |= 2;
+        }
+        if (!isfinite(t_end) || !isfinite(dt0))
+            flag |= 1;
+        else if (t_end < 0.0 || !(dt0 > 0.0))
+            flag |= 2;
+        flag = wave_or(flag);
+        if (lane == 0)
+            wave_flag[wave] = flag;
+        __syncthreads();
+        flag = 0;
+#pragma unroll
+        for (int w = 0; w < NWAVES; ++w)
+            flag |= wave_flag[w];
+        if (flag) {
+            if (tid == 0) {
+                za.status[z] = (flag & 1) ? kZoneNonfinite : kZoneBadInput;
+                za.n_acc[z] = 0;
+                za.n_rej[z] = 0;
+            }
+            __syncthreads();  // keeps the lane-0 block off the loop back edge
+            continue;         // Y and dt stay as given
+        }
+
+        // ---- integrate over [0, t_end]
+        double t = 0.0, step = dt0;
+        int64_t nacc = 0, nrej = 0;
+        int32_t status = kZoneOk;
+        for (;;) {
+            if (t >= t_end) {
+                status = kZoneOk;
+                break;
+            }
+            if (nacc + nrej >= o.max_steps) {
+                status = kZoneMaxSteps;
+                break;
+            }
+            const bool clipped = step >= t_end - t;
+            const double h = clipped ? t_end - t : step;
+            double rloc = 0.0;
+            bool bad = false;
+            for (int i = tid; i < N; i += NTHREADS) {
+                // creation flux F+_i: fluxes of the reactions producing i
+                double fp = 0.0;
+                const int pe = net.prod_ptr[i + 1];
+                for (int e = net.prod_ptr[i]; e < pe; ++e) {
+                    const int b = net.prod_b[e];
+                    double f = k[net.prod_rx[e]] * Y[net.prod_a[e]];
+                    if (b >= 0)
+                        f = f * Y[b];
+                    fp = fp + f;
+                }
+                // depletion rate k_i: F-_i / Y_i summed from the reactions destroying i
+                double kd = 0.0;
+                const int de = net.dest_ptr[i + 1];
+                for (int e = net.dest_ptr[i]; e < de; ++e) {
+                    const int oth = net.dest_o[e];
+                    const double kj = k[net.dest_rx[e]];
+                    kd = kd + (oth >= 0 ? kj * Y[oth] : kj);
+                }
+                const double y = Y[i];
+                const double kh = kd * h;
+                double yn;
+                if (kh < o.kappa)
+                    yn = y + h * (fp - kd * y);    // forward Euler
+                else
+                    yn = (y + h * fp) / (1.0 + kh); // asymptotic form
+                Yn[i] = yn;
+                if (!isfinite(yn))
+                    bad = true;
+                else
+                    rloc = fmax(rloc, fabs(yn - y) / fmax(y, o.y_floor));
+            }
+            if (bad)
+                rloc = INFINITY;
+            rloc = wave_max(rloc);
+            if (lane == 0)
+                wave_r[wave] = rloc;
+            __syncthreads();
+            double r = wave_r[0];
+#pragma unroll
+            for (int w = 1; w < NWAVES; ++w)
+                r = fmax(r, wave_r[w]);
+            if (r <= o.tol) {
+                for (int i = tid; i < N; i += NTHREADS)
+                    Y[i] = Yn[i];
+                ++nacc;
+                t = clipped ? t_end : t + h;
+                if (!clipped) {
+                    const double g = (r == 0.0) ? o.grow_max : fmin(o.grow_max, o.safety * o.tol / r);
+                    step = h * g;
+                }
+            } else {
+                ++nrej;
+                const double s = isinf(r) ? o.shrink_min : fmax(o.shrink_min, o.safety * o.tol / r);
+                step = h * s;
+                if (step < o.dt_min) {
+                    status = kZoneDtUnderflow;
+                    break;
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        double *Yo = za.Y + (size_t)z * N;
+        for (int i = tid; i < N; i += NTHREADS)
+            Yo[i] = Y[i];
+        if (tid == 0) {
+            za.dt[z] = step;
+            za.n_acc[z] = nacc;
+            za.n_rej[z] = nrej;
+            za.status[z] = status;
+        }
+        // A convergent point between the lane-0 stores above and the zone
+        // fetch at the loop head: without it the compiler may thread the
+        // lane-0 condition across the back edge and let the other lanes
+        // re-read a stale zone index.
+        __syncthreads();
+    }
+}
+
+}  // namespace asynet

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP integrator against the CPU oracle on the same seeded zones.
+
+Bar: for every species whose oracle abundance exceeds 1e-20, relative error
+<= 1e-9; accepted steps within 1% per zone; identical zone status; next-step
+dt within 1e-9.  Both sides evaluate the same FP64 expressions in the same
+order without contraction, so most zones agree bit for bit; the tolerance
+absorbs the last-bit differences of exp() between the device and host math
+libraries in the Arrhenius rates.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_5826_amd import binding, workloads
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-9
+Y_MIN = 1e-20
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+
+    assert torch.cuda.is_available(), "gpu tests need a device"
+    binding.lib()
+    yield
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(wl, opts=None, launch=None, zones=None):
+    import torch
+
+    zones = wl.zones if zones is None else zones
+    net = binding.Network(wl.network)
+    try:
+        if launch:
+            net.set_launch(**launch)
+        buf = net.zone_buffers(zones)
+        net.integrate(buf, opts)
+        torch.cuda.synchronize()
+        return {k: (None if v is None else v.cpu().numpy()) for k, v in buf.items()}
+    finally:
+        net.close()
+
+
+def oracle_opts(o):
+    if o is None:
+        return oracle.options()
+    return oracle.options(kappa=o.kappa, tol=o.tol, y_floor=o.y_floor, grow_max=o.grow_max,
+                          safety=o.safety, shrink_min=o.shrink_min, dt_min=o.dt_min,
+                          max_steps=o.max_steps)
+
+
+def compare(g, ref, idx=None):
+    """Assert parity of GPU outputs g (optionally rows idx) with oracle outputs ref."""
+    sel = slice(None) if idx is None else np.asarray(idx)
+    gY, gacc, grej = g["Y"][sel], g["n_accepted"][sel], g["n_rejected"][sel]
+    gst, gdt = g["zone_status"][sel], g["dt"][sel]
+    np.testing.assert_array_equal(gst, ref["status"])
+    assert (np.abs(gacc - ref["n_acc"]) <= 0.01 * ref["n_acc"]).all()
+    big = ref["Y"] > Y_MIN
+    rel = np.abs(gY - ref["Y"])[big] / ref["Y"][big]
+    assert rel.max(initial=0.0) <= REL_TOL, f"max rel err {rel.max():.3e}"
+    np.testing.assert_allclose(gdt, ref["dt"], rtol=REL_TOL, atol=0)
+    exact = np.mean([np.array_equal(gY[i], ref["Y"][i]) for i in range(len(gY))])
+    return dict(max_rel=float(rel.max(initial=0.0)), bit_exact_zones=float(exact),
+                steps=int(ref["n_acc"].sum()))
+
+
+def test_n16_single_zone():
+    wl = workloads.preset("n16_r48_const")
+    say(f"case n16_r48_const zones={wl.zones.n_zones}")
+    g = run_gpu(wl)
+    ref = oracle.integrate_batch(wl.network, wl.zones)
+    info = compare(g, ref)
+    assert info["bit_exact_zones"] == 1.0   # constant rates: identical arithmetic
+    assert g["n_accepted"][0] == ref["n_acc"][0] and g["n_rejected"][0] == ref["n_rej"][0]
+
+
+def test_n150_constant_rates_128_zones():
+    wl = workloads.preset("n150_r1604_const")
+    say(f"case n150_r1604_const zones={wl.zones.n_zones}")
+    g = run_gpu(wl)
+    ref = oracle.integrate_batch(wl.network, wl.zones)
+    info = compare(g, ref)
+    assert info["bit_exact_zones"] == 1.0
+    np.testing.assert_array_equal(g["n_accepted"], ref["n_acc"])
+    np.testing.assert_array_equal(g["n_rejected"], ref["n_rej"])
+
+
+@pytest.mark.parametrize("name,n_sample", [("n150_r1604_arrhenius", 40), ("n365_r4400_arrhenius", 16)])
+def test_arrhenius_full_size_sampled(name, n_sample):
+    """Full zone count in the default launch configuration; oracle on sampled zones."""
+    wl = workloads.preset(name)
+    say(f"case {name} zones={wl.zones.n_zones} sample={n_sample}")
+    g = run_gpu(wl)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(wl.zones.n_zones, n_sample, replace=False))
+    ref = oracle.integrate_batch(wl.network, wl.zones.subset(idx))
+    compare(g, ref, idx)
+    assert (g["zone_status"] == binding.ZONE_OK).all()
+    assert (g["Y"] >= 0).all()
+
+
+def test_arrhenius_small_batch_all_zones():
+    wl = workloads.preset("n150_r1604_arrhenius", n_zones=67)   # ragged: not a multiple of anything
+    say("case n150_r1604_arrhenius zones=67 all")
+    g = run_gpu(wl)
+    ref = oracle.integrate_batch(wl.network, wl.zones)
+    compare(g, ref)
+
+
+LAUNCHES = [
+    dict(threads_per_zone=64, groups_per_cu=0),
+    dict(threads_per_zone=128, groups_per_cu=1),
+    dict(threads_per_zone=256, groups_per_cu=2),
+    dict(threads_per_zone=512, groups_per_cu=0),
+]
+
+
+def test_placement_invariance_and_determinism():
+    """Launch configuration changes only the speed: results are bit-identical."""
+    wl = workloads.preset("n150_r1604_const", n_zones=24)
+    say("case placement n150_r1604_const zones=24")
+    outs = [run_gpu(wl, launch=c) for c in LAUNCHES]
+    outs.append(run_gpu(wl, launch=LAUNCHES[0]))
+    for o in outs[1:]:
+        for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
+            np.testing.assert_array_equal(o[key], outs[0][key])
+
+
+def test_edge_cases_statuses():
+    """Bad inputs, budgets and degenerate intervals, zone by zone, against the oracle."""
+    wl = workloads.preset("n150_r1604_const", n_zones=8)
+    z = wl.zones
+    z.Y0[1, 7] = np.nan          # non-finite abundance
+    z.Y0[2, 3] = -1e-3           # negative abundance
+    z.k[3, 11] = np.inf          # non-finite rate
+    z.t_end[4] = 0.0             # empty interval
+    z.dt0[5] = 0.0               # invalid trial step
+    z.t_end[6] = 1e-9            # interval shorter than a few steps
+    z.dt0[7] = 10.0              # trial step larger than the interval (clipped first step)
+    say("case edge statuses")
+    g = run_gpu(wl)
+    ref = oracle.integrate_batch(wl.network, z)
+    assert list(ref["status"][:6]) == [0, 3, 4, 3, 0, 4]
+    compare(g, ref)
+    np.testing.assert_array_equal(g["Y"][1:4], z.Y0[1:4])  # untouched on input failure
+
+
+@pytest.mark.parametrize("kw,status", [(dict(max_steps=50), binding.ZONE_MAX_STEPS),
+                                       (dict(dt_min=1e-6), binding.ZONE_DT_UNDERFLOW)])
+def test_budget_statuses(kw, status):
+    wl = workloads.preset("n150_r1604_const", n_zones=4)
+    opts = binding.options_default(**kw)
+    say(f"case budget {kw}")
+    g = run_gpu(wl, opts=opts)
+    ref = oracle.integrate_batch(wl.network, wl.zones, oracle_opts(opts))
+    assert (ref["status"] == status).all()
+    compare(g, ref)
+
+
+def test_euler_only_and_tight_tolerance():
+    wl = workloads.preset("n16_r48_const")
+    for kw in (dict(kappa=math.inf, max_steps=2000), dict(tol=1e-4)):
+        opts = binding.options_default(**kw)
+        say(f"case n16 options {kw}")
+        g = run_gpu(wl, opts=opts)
+        ref = oracle.integrate_batch(wl.network, wl.zones, oracle_opts(opts))
+        compare(g, ref)
+
+
+def test_zero_zones_is_a_no_op():
+    import torch
+
+    wl = workloads.preset("n16_r48_const")
+    net = binding.Network(wl.network)
+    try:
+        e = torch.empty((0, 16), dtype=torch.float64, device="cuda")
+        z = torch.empty(0, dtype=torch.float64, device="cuda")
+        i64 = torch.empty(0, dtype=torch.int64, device="cuda")
+        i32 = torch.empty(0, dtype=torch.int32, device="cuda")
+        kz = torch.empty((0, 48), dtype=torch.float64, device="cuda")
+        binding.asy_integrate_batch(net.handle, 16, 48, e, z, z, i64, i64, i32, k_zone=kz)
+        torch.cuda.synchronize()
+    finally:
+        net.close()
