@@ -49,10 +49,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n150_r1604_arrhenius")
     ap.add_argument("--zones", type=int, default=None)
-    ap.add_argument("--cpu-sample-stride", type=int, default=16,
+    ap.add_argument("--cpu-sample-stride", type=int, default=4,
                     help="oracle baseline integrates every Nth zone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None, help="JSON dict of asy_launch fields")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate launch configurations on the workload first")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -73,6 +75,9 @@ def main(argv=None):
     buf = net.zone_buffers(wl.zones)
     Y0 = buf["Y"].clone()
     dt0 = buf["dt"].clone()
+    if args.autotune:
+        binding.asy_autotune(net.handle, net.n_species, net.n_reactions, Y0, buf["t_end"], dt0,
+                             T=buf["T"], k_zone=buf["k_zone"])
     stream = torch.cuda.current_stream()
 
     def step():

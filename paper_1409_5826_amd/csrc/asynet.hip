@@ -1,10 +1,9 @@
-// Host side of the asynet C ABI: descriptor validation, species-major
-// incidence build, device upload, launch configuration, graph replay and
-// autotuning.  See include/asynet.h for the contract of every entry point.
+// Host side of the asynet C ABI: descriptor validation, incidence layouts,
+// device upload, launch configuration, graph replay and autotuning.  See
+// include/asynet.h for the contract of every entry point.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -13,6 +12,7 @@
 
 #include "asynet.h"
 #include "integrate_kernels.h"
+#include "stratified_kernel.h"
 
 using namespace asynet;
 
@@ -34,6 +34,20 @@ asy_status fail(asy_status st, const std::string &msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));              \
     } while (0)
 
+// Layout of variant 1 for one choice of waves per zone.
+struct StratLayout {
+    int W = 0, lanes = 0, K = 0, C_needed = 0, C = 0, SPL = 0;
+    void *dev = nullptr;
+    StratNetwork sn{};
+    bool ok = false;
+};
+
+// Captured launch sequence for repeated identical calls.
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint8_t> key;
+};
+
 }  // namespace
 
 struct asy_network {
@@ -44,44 +58,208 @@ struct asy_network {
     int device = 0;
     int n_cu = 0;
     size_t lds_per_group_max = 0;
-    // device arrays (one allocation, carved)
-    void *dev_block = nullptr;
+    void *dev_block = nullptr;  // network structure (variant 0) and the zone queue
     int32_t *queue = nullptr;
     DevNetwork dn{};
+    StratLayout strat[3];       // variant 1 with W = 1, 2, 4
+    double *rate_buf = nullptr; // Arrhenius rates of one call, [zones][reactions]
+    size_t rate_buf_zones = 0;
     asy_launch launch{};
-    // host copies of the structure (for validation of launches and autotuning)
-    std::vector<int32_t> prod_ptr, dest_ptr;
-    // graph replay cache
     hipStream_t capture_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    std::vector<uint8_t> graph_key;
+    GraphCache graph;
 };
 
 namespace {
+
+// ---- variant 1 kernel instances -----------------------------------------------------------
+
+using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *);
+
+struct StratInstance {
+    int W, SPL, C;
+    StratKernel fn;
+};
+
+#define ASY_STRAT(W_, SPL_, C_) {W_, SPL_, C_, integrate_strat_kernel<W_, SPL_, C_>}
+const StratInstance kStratInstances[] = {
+    ASY_STRAT(1, 1, 16), ASY_STRAT(1, 1, 32), ASY_STRAT(1, 2, 32), ASY_STRAT(1, 2, 64),
+    ASY_STRAT(1, 3, 64), ASY_STRAT(1, 3, 104), ASY_STRAT(1, 3, 112), ASY_STRAT(1, 4, 64),
+    ASY_STRAT(2, 1, 32), ASY_STRAT(2, 2, 48), ASY_STRAT(2, 2, 64), ASY_STRAT(2, 2, 72),
+    ASY_STRAT(2, 2, 80), ASY_STRAT(2, 3, 64), ASY_STRAT(2, 3, 96), ASY_STRAT(2, 3, 136),
+    ASY_STRAT(4, 1, 32), ASY_STRAT(4, 1, 48), ASY_STRAT(4, 1, 56), ASY_STRAT(4, 1, 64),
+    ASY_STRAT(4, 2, 48), ASY_STRAT(4, 2, 64), ASY_STRAT(4, 2, 80), ASY_STRAT(4, 2, 96),
+};
+#undef ASY_STRAT
+
+const StratInstance *find_strat_instance(int W, int SPL, int C_needed)
+{
+    const StratInstance *best = nullptr;
+    for (const auto &in : kStratInstances)
+        if (in.W == W && in.SPL == SPL && in.C >= C_needed && (!best || in.C < best->C))
+            best = &in;
+    return best;
+}
+
+int w_index(int W) { return W == 1 ? 0 : (W == 2 ? 1 : 2); }
+
+// Rows of the network: row i (< N) sums the creation flux of species i, row
+// N + i its depletion rate; terms in ascending reaction index.  A term is
+// (rx, x, y) with x, y LDS cells of Y (cell N holds 1.0).
+struct Term {
+    int32_t rx, x, y;
+};
+
+std::vector<std::vector<Term>> network_rows(int N, int R, const int32_t *r0, const int32_t *r1,
+                                            const int32_t *pr)
+{
+    std::vector<std::vector<Term>> rows(2 * (size_t)N);
+    for (int j = 0; j < R; ++j) {  // ascending j keeps every row in reaction order
+        const int a = r0[j], b = r1[j], c = pr[j];
+        rows[c].push_back({j, a, b >= 0 ? b : N});
+        rows[N + a].push_back({j, b >= 0 ? b : N, N});
+        if (b >= 0)
+            rows[N + b].push_back({j, a, N});
+    }
+    return rows;
+}
+
+// Deal the rows out in strata of 64*W lanes, longest rows first.  Leaves
+// L.ok false when no compiled instance can hold the layout.
+void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows)
+{
+    StratLayout &L = net->strat[w_index(W)];
+    L = StratLayout{};
+    const int N = net->n_species;
+    const int lanes = 64 * W;
+    std::vector<int> order(rows.size());
+    for (size_t r = 0; r < rows.size(); ++r)
+        order[r] = (int)r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return rows[a].size() > rows[b].size(); });
+    const int K = (int)((rows.size() + lanes - 1) / lanes);
+    std::vector<int32_t> strat_end(K);
+    int slot = 0;
+    for (int k = 0; k < K; ++k) {
+        size_t len = 1;  // every stratum closes at a slot, even when all its rows are empty
+        for (int l = 0; l < lanes; ++l) {
+            const size_t r = (size_t)k * lanes + l;
+            if (r < order.size())
+                len = std::max(len, rows[order[r]].size());
+        }
+        slot += (int)((len + 3) / 4 * 4);  // strata end on multiples of 4 slots
+        strat_end[k] = slot;
+    }
+    if ((N + 1) * 8 > 65535)
+        return;  // byte offsets of Y cells must fit 16 bits
+    L.W = W;
+    L.lanes = lanes;
+    L.K = K;
+    L.C_needed = slot;
+    L.SPL = (N + lanes - 1) / lanes;
+    const StratInstance *inst = find_strat_instance(W, L.SPL, L.C_needed);
+    if (!inst)
+        return;
+    const int C = inst->C;
+    L.C = C;
+    // descriptors hold byte offsets of the two Y cells (cell N = 1.0)
+    const uint32_t one = (uint32_t)N * 8u;
+    std::vector<uint32_t> desc((size_t)C * lanes, one | (one << 16));
+    std::vector<int32_t> rx((size_t)C * lanes, -1);
+    std::vector<int32_t> dst((size_t)K * lanes, 2 * N);
+    int start = 0;
+    for (int k = 0; k < K; ++k) {
+        for (int l = 0; l < lanes; ++l) {
+            const size_t r = (size_t)k * lanes + l;
+            if (r >= order.size())
+                continue;
+            const int row = order[r];
+            dst[(size_t)k * lanes + l] = row;
+            const auto &terms = rows[row];
+            for (size_t e = 0; e < terms.size(); ++e) {
+                const size_t at = (size_t)(start + (int)e) * lanes + l;
+                desc[at] = (uint32_t)terms[e].x * 8u | ((uint32_t)terms[e].y * 8u << 16);
+                rx[at] = terms[e].rx;
+            }
+        }
+        start = strat_end[k];
+    }
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_desc = carve(desc.size() * 4), o_rx = carve(rx.size() * 4);
+    const size_t o_end = carve(strat_end.size() * 4), o_dst = carve(dst.size() * 4);
+    if (hipMalloc(&L.dev, off) != hipSuccess) {
+        L.dev = nullptr;
+        return;
+    }
+    char *base = static_cast<char *>(L.dev);
+    hipError_t e = hipSuccess;
+    auto put = [&](size_t o, const void *src, size_t bytes) {
+        if (e == hipSuccess)
+            e = hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
+    };
+    put(o_desc, desc.data(), desc.size() * 4);
+    put(o_rx, rx.data(), rx.size() * 4);
+    put(o_end, strat_end.data(), strat_end.size() * 4);
+    put(o_dst, dst.data(), dst.size() * 4);
+    if (e != hipSuccess)
+        return;
+    L.sn.n_species = N;
+    L.sn.n_reactions = net->n_reactions;
+    L.sn.n_strata = K;
+    L.sn.n_slots = L.C_needed;
+    L.sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc);
+    L.sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
+    L.sn.strat_end = reinterpret_cast<const int32_t *>(base + o_end);
+    L.sn.strat_dst = reinterpret_cast<const int32_t *>(base + o_dst);
+    L.ok = true;
+}
 
 size_t lds_bytes_variant0(const asy_network *net)
 {
     return sizeof(double) * ((size_t)net->n_reactions + 2 * (size_t)net->n_species);
 }
 
+size_t lds_bytes_variant1(const asy_network *net, int zones_per_group)
+{
+    return sizeof(double) * (size_t)strat_zone_cells(net->n_species) * zones_per_group;
+}
+
 asy_status validate_launch(const asy_network *net, const asy_launch *c)
 {
     if (c->reserved != 0)
         return fail(ASY_EINVAL, "asy_launch.reserved must be 0");
-    if (c->variant != 0)
-        return fail(ASY_EINVAL, "asy_launch.variant must be 0");
-    if (c->threads_per_zone != 64 && c->threads_per_zone != 128 && c->threads_per_zone != 256 &&
-        c->threads_per_zone != 512)
-        return fail(ASY_EINVAL, "asy_launch.threads_per_zone must be 64, 128, 256 or 512");
-    if (c->zones_per_group != 1)
-        return fail(ASY_EINVAL, "asy_launch.zones_per_group must be 1 for variant 0");
     if (c->groups_per_cu < 0 || c->groups_per_cu > 32)
         return fail(ASY_EINVAL, "asy_launch.groups_per_cu must be in [0, 32]");
     if (c->use_graph != 0 && c->use_graph != 1)
         return fail(ASY_EINVAL, "asy_launch.use_graph must be 0 or 1");
-    if (lds_bytes_variant0(net) > net->lds_per_group_max)
-        return fail(ASY_ENOTSUP, "network too large for the LDS of one workgroup");
-    return ASY_OK;
+    if (c->variant == 0) {
+        if (c->threads_per_zone != 64 && c->threads_per_zone != 128 &&
+            c->threads_per_zone != 256 && c->threads_per_zone != 512)
+            return fail(ASY_EINVAL, "variant 0: threads_per_zone must be 64, 128, 256 or 512");
+        if (c->zones_per_group != 1)
+            return fail(ASY_EINVAL, "variant 0: zones_per_group must be 1");
+        if (lds_bytes_variant0(net) > net->lds_per_group_max)
+            return fail(ASY_ENOTSUP, "variant 0: network too large for the LDS of one workgroup");
+        return ASY_OK;
+    }
+    if (c->variant == 1) {
+        const int W = c->threads_per_zone / 64;
+        if (c->threads_per_zone % 64 || (W != 1 && W != 2 && W != 4))
+            return fail(ASY_EINVAL, "variant 1: threads_per_zone must be 64, 128 or 256");
+        if (c->zones_per_group != 1)
+            return fail(ASY_EINVAL, "variant 1: zones_per_group must be 1");
+        if (!net->strat[w_index(W)].ok)
+            return fail(ASY_ENOTSUP, "variant 1 has no kernel instance for this network with " +
+                                         std::to_string(c->threads_per_zone) + " threads per zone");
+        if (lds_bytes_variant1(net, c->zones_per_group) > net->lds_per_group_max)
+            return fail(ASY_ENOTSUP, "variant 1: zones do not fit the LDS of one workgroup");
+        return ASY_OK;
+    }
+    return fail(ASY_EINVAL, "asy_launch.variant must be 0 or 1");
 }
 
 template <int NT, bool ARR>
@@ -93,6 +271,8 @@ hipError_t launch_variant0(asy_network *net, const DevOptions &o, const ZoneArgs
     return hipGetLastError();
 }
 
+// Queue every kernel of one call on stream s (no allocation, no host sync, so
+// the sequence can be captured into a graph).
 hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o,
                       const ZoneArgs &za, hipStream_t s)
 {
@@ -100,6 +280,29 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
+    if (c.variant == 1) {
+        const int W = c.threads_per_zone / 64;
+        const StratLayout &L = net->strat[w_index(W)];
+        const double *rates = za.k_zone;
+        if (net->rate_form == ASY_RATES_ARRHENIUS) {
+            const size_t total = (size_t)za.n_zones * net->n_reactions;
+            const int blocks = (int)std::min<size_t>((total + 255) / 256, (size_t)net->n_cu * 16);
+            hipLaunchKernelGGL(rates_arrhenius_kernel, dim3(blocks), dim3(256), 0, s, za.n_zones,
+                               net->n_reactions, net->dn.A, net->dn.E, za.T, net->rate_buf);
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+            rates = net->rate_buf;
+        }
+        const StratInstance *inst = find_strat_instance(W, L.SPL, L.C);
+        const int zpg = c.zones_per_group;
+        int grid = (za.n_zones + zpg - 1) / zpg;
+        if (c.groups_per_cu > 0)
+            grid = std::min(grid, c.groups_per_cu * net->n_cu);
+        hipLaunchKernelGGL(inst->fn, dim3(grid), dim3(c.threads_per_zone * zpg),
+                           lds_bytes_variant1(net, zpg), s, L.sn, o, za, rates);
+        return hipGetLastError();
+    }
     int grid = za.n_zones;
     if (c.groups_per_cu > 0)
         grid = std::min(grid, c.groups_per_cu * net->n_cu);
@@ -144,6 +347,83 @@ asy_status validate_options(const asy_options *o)
     return ASY_OK;
 }
 
+// Make the Arrhenius rate table large enough for n_zones (synchronizes the
+// stream before replacing a table a queued call may still read).
+asy_status ensure_rate_buf(asy_network *net, int32_t n_zones, hipStream_t s)
+{
+    if (net->rate_form != ASY_RATES_ARRHENIUS || net->rate_buf_zones >= (size_t)n_zones)
+        return ASY_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (net->graph.exec) {  // a captured graph holds the old table's address
+        HIP_TRY(hipGraphExecDestroy(net->graph.exec));
+        net->graph.exec = nullptr;
+        net->graph.key.clear();
+    }
+    if (net->rate_buf)
+        HIP_TRY(hipFree(net->rate_buf));
+    net->rate_buf = nullptr;
+    net->rate_buf_zones = 0;
+    HIP_TRY(hipMalloc(&net->rate_buf, sizeof(double) * (size_t)n_zones * net->n_reactions));
+    net->rate_buf_zones = (size_t)n_zones;
+    return ASY_OK;
+}
+
+template <typename T>
+void append_bytes(std::vector<uint8_t> &key, const T &v)
+{
+    const uint8_t *p = reinterpret_cast<const uint8_t *>(&v);
+    key.insert(key.end(), p, p + sizeof(T));
+}
+
+// Queue one call, replaying a captured graph when the launch is identical to
+// the previous one (same configuration, options, sizes and buffers).
+asy_status enqueue(asy_network *net, const asy_launch &c, const DevOptions &o, const ZoneArgs &za,
+                   hipStream_t s)
+{
+    if (!c.use_graph) {
+        HIP_TRY(launch_all(net, c, o, za, s));
+        return ASY_OK;
+    }
+    std::vector<uint8_t> key;
+    append_bytes(key, c);
+    append_bytes(key, o);
+    append_bytes(key, za);
+    if (net->graph.exec == nullptr || key != net->graph.key) {
+        if (net->graph.exec) {
+            HIP_TRY(hipGraphExecDestroy(net->graph.exec));
+            net->graph.exec = nullptr;
+            net->graph.key.clear();
+        }
+        if (!net->capture_stream)
+            HIP_TRY(hipStreamCreateWithFlags(&net->capture_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(net->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = launch_all(net, c, o, za, net->capture_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(net->capture_stream, &graph);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return fail(ASY_EDEVICE, std::string("graph capture: ") +
+                                         hipGetErrorString(le != hipSuccess ? le : ee));
+        }
+        hipError_t ie = hipGraphInstantiate(&net->graph.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            net->graph.exec = nullptr;
+            return fail(ASY_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        }
+        net->graph.key = key;
+    }
+    HIP_TRY(hipGraphLaunch(net->graph.exec, s));
+    return ASY_OK;
+}
+
+DevOptions to_dev(const asy_options &o)
+{
+    return DevOptions{o.kappa, o.tol, o.y_floor, o.grow_max, o.safety, o.shrink_min, o.dt_min,
+                      o.max_steps};
+}
+
 }  // namespace
 
 extern "C" {
@@ -166,7 +446,7 @@ void asy_options_default(asy_options *o)
 
 const char *asy_last_error(void) { return g_last_error.c_str(); }
 
-const char *asy_version(void) { return "asynet 0.1 (gfx950)"; }
+const char *asy_version(void) { return "asynet 0.2 (gfx950)"; }
 
 asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
 {
@@ -176,8 +456,8 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     const int32_t N = d->n_species, R = d->n_reactions;
     if (N < 1 || R < 1)
         return fail(ASY_EINVAL, "n_species and n_reactions must be >= 1");
-    if (N > 32767 || R > (1 << 24))
-        return fail(ASY_EINVAL, "network too large (n_species <= 32767, n_reactions <= 2^24)");
+    if (N > 32000 || R > (1 << 24))
+        return fail(ASY_EINVAL, "network too large (n_species <= 32000, n_reactions <= 2^24)");
     if (!d->reactant0 || !d->reactant1 || !d->product)
         return fail(ASY_EINVAL, "reactant0, reactant1 and product must be non-NULL");
     if (d->rate_form == ASY_RATES_ARRHENIUS) {
@@ -211,7 +491,7 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     }
     const int32_t D = R + n_two;
 
-    // species-major incidence, ascending reaction index within each row
+    // variant 0 layout: species-major rows, ascending reaction index within each row
     std::vector<int32_t> prod_ptr(N + 1, 0), dest_ptr(N + 1, 0);
     for (int32_t j = 0; j < R; ++j) {
         prod_ptr[d->product[j] + 1]++;
@@ -227,7 +507,7 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     {
         std::vector<int32_t> pf(prod_ptr.begin(), prod_ptr.end() - 1);
         std::vector<int32_t> df(dest_ptr.begin(), dest_ptr.end() - 1);
-        for (int32_t j = 0; j < R; ++j) {  // ascending j keeps each row sorted
+        for (int32_t j = 0; j < R; ++j) {
             const int32_t a = d->reactant0[j], b = d->reactant1[j], c = d->product[j];
             int32_t e = pf[c]++;
             prod_rx[e] = j;
@@ -244,7 +524,7 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
         }
     }
 
-    // device: check for a gfx950 device before allocating
+    // device: require gfx950 before allocating anything
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess)
@@ -265,10 +545,7 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     net->device = dev;
     net->n_cu = prop.multiProcessorCount;
     net->lds_per_group_max = prop.sharedMemPerBlock;
-    net->prod_ptr = prod_ptr;
-    net->dest_ptr = dest_ptr;
 
-    // one device allocation, 256-byte aligned pieces
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
@@ -292,29 +569,26 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
         return fail(ASY_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(he));
     }
     char *base = static_cast<char *>(net->dev_block);
-    auto put = [&](size_t o, const void *src, size_t bytes) {
-        return hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
-    };
     hipError_t ce = hipSuccess;
-    auto chk = [&](hipError_t e) {
+    auto put = [&](size_t o, const void *src, size_t bytes) {
         if (ce == hipSuccess)
-            ce = e;
+            ce = hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
     };
-    chk(hipMemset(base + o_queue, 0, 256));
-    chk(put(o_pp, prod_ptr.data(), sizeof(int32_t) * (N + 1)));
-    chk(put(o_prx, prod_rx.data(), sizeof(int32_t) * R));
-    chk(put(o_pa, prod_a.data(), sizeof(int32_t) * R));
-    chk(put(o_pb, prod_b.data(), sizeof(int32_t) * R));
-    chk(put(o_dp, dest_ptr.data(), sizeof(int32_t) * (N + 1)));
-    chk(put(o_drx, dest_rx.data(), sizeof(int32_t) * D));
-    chk(put(o_do, dest_o.data(), sizeof(int32_t) * D));
+    if (ce == hipSuccess)
+        ce = hipMemset(base + o_queue, 0, 256);
+    put(o_pp, prod_ptr.data(), sizeof(int32_t) * (N + 1));
+    put(o_prx, prod_rx.data(), sizeof(int32_t) * R);
+    put(o_pa, prod_a.data(), sizeof(int32_t) * R);
+    put(o_pb, prod_b.data(), sizeof(int32_t) * R);
+    put(o_dp, dest_ptr.data(), sizeof(int32_t) * (N + 1));
+    put(o_drx, dest_rx.data(), sizeof(int32_t) * D);
+    put(o_do, dest_o.data(), sizeof(int32_t) * D);
     if (arr) {
-        chk(put(o_A, d->A, sizeof(double) * R));
-        chk(put(o_E, d->E, sizeof(double) * R));
+        put(o_A, d->A, sizeof(double) * R);
+        put(o_E, d->E, sizeof(double) * R);
     }
     if (ce != hipSuccess) {
-        (void)hipFree(net->dev_block);
-        delete net;
+        asy_network_destroy(net);
         return fail(ASY_EDEVICE, std::string("upload: ") + hipGetErrorString(ce));
     }
     net->queue = reinterpret_cast<int32_t *>(base + o_queue);
@@ -331,15 +605,28 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     dn.A = arr ? reinterpret_cast<const double *>(base + o_A) : nullptr;
     dn.E = arr ? reinterpret_cast<const double *>(base + o_E) : nullptr;
 
-    net->launch.variant = 0;
-    net->launch.threads_per_zone = N <= 64 ? 64 : (N <= 128 ? 128 : 256);
-    net->launch.zones_per_group = 1;
-    net->launch.groups_per_cu = 0;
-    net->launch.use_graph = 0;
-    net->launch.reserved = 0;
+    // variant 1 layouts
+    {
+        const auto rows = network_rows(N, R, d->reactant0, d->reactant1, d->product);
+        for (int W : {1, 2, 4})
+            build_strat(net, W, rows);
+    }
+    // default launch: variant 1 with the fewest waves per zone that has an
+    // instance, else the generic variant 0
+    asy_launch c{};
+    c.variant = 0;
+    c.threads_per_zone = N <= 64 ? 64 : (N <= 128 ? 128 : 256);
+    c.zones_per_group = 1;
+    for (int W : {1, 2, 4}) {
+        if (net->strat[w_index(W)].ok) {
+            c.variant = 1;
+            c.threads_per_zone = 64 * W;
+            break;
+        }
+    }
+    net->launch = c;
     if (validate_launch(net, &net->launch) != ASY_OK) {
-        (void)hipFree(net->dev_block);
-        delete net;
+        asy_network_destroy(net);
         return fail(ASY_ENOTSUP, "network too large for the LDS of one workgroup");
     }
     *out = net;
@@ -351,12 +638,17 @@ void asy_network_destroy(asy_network *net)
     if (!net)
         return;
     (void)hipDeviceSynchronize();
-    if (net->graph_exec)
-        (void)hipGraphExecDestroy(net->graph_exec);
+    if (net->graph.exec)
+        (void)hipGraphExecDestroy(net->graph.exec);
     if (net->capture_stream)
         (void)hipStreamDestroy(net->capture_stream);
     if (net->dev_block)
         (void)hipFree(net->dev_block);
+    for (auto &L : net->strat)
+        if (L.dev)
+            (void)hipFree(L.dev);
+    if (net->rate_buf)
+        (void)hipFree(net->rate_buf);
     delete net;
 }
 
@@ -406,25 +698,110 @@ asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_
     } else if (!k_zone || T) {
         return fail(ASY_EINVAL, "per-zone-rate networks take k_zone and no T");
     }
-    DevOptions dop{o.kappa, o.tol, o.y_floor, o.grow_max, o.safety, o.shrink_min, o.dt_min,
-                   o.max_steps};
     ZoneArgs za{n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected, zone_status, net->queue};
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(net->device));
-    HIP_TRY(launch_all(net, net->launch, dop, za, s));
-    return ASY_OK;
+    if (net->launch.variant == 1) {
+        st = ensure_rate_buf(net, n_zones, s);
+        if (st != ASY_OK)
+            return st;
+    }
+    return enqueue(net, net->launch, to_dev(o), za, s);
 }
 
 asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sample_zones,
                         const double *Y, const double *T, const double *k_zone,
                         const double *t_end, const double *dt, asy_launch *best)
 {
-    (void)opts; (void)sample_zones; (void)Y; (void)T; (void)k_zone; (void)t_end; (void)dt;
+    g_last_error.clear();
     if (!net)
         return fail(ASY_EINVAL, "net must be non-NULL");
+    asy_options o;
+    asy_options_default(&o);
+    if (opts)
+        o = *opts;
+    asy_status st = validate_options(&o);
+    if (st != ASY_OK)
+        return st;
+    if (sample_zones < 1)
+        return fail(ASY_EINVAL, "sample_zones must be >= 1");
+    if (!Y || !t_end || !dt)
+        return fail(ASY_EINVAL, "Y, t_end and dt must be non-NULL");
+    if (net->rate_form == ASY_RATES_ARRHENIUS ? (!T || k_zone) : (!k_zone || T))
+        return fail(ASY_EINVAL, "rate arguments do not match the network's rate form");
+    HIP_TRY(hipSetDevice(net->device));
+    const int Z = sample_zones;
+    const size_t nY = (size_t)Z * net->n_species;
+    // private copies: the integration works in place
+    double *wY = nullptr, *wdt = nullptr;
+    int64_t *wacc = nullptr, *wrej = nullptr;
+    int32_t *wst = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(wY);
+        (void)hipFree(wdt);
+        (void)hipFree(wacc);
+        (void)hipFree(wrej);
+        (void)hipFree(wst);
+    };
+    if (hipMalloc(&wY, nY * 8) != hipSuccess || hipMalloc(&wdt, (size_t)Z * 8) != hipSuccess ||
+        hipMalloc(&wacc, (size_t)Z * 8) != hipSuccess || hipMalloc(&wrej, (size_t)Z * 8) != hipSuccess ||
+        hipMalloc(&wst, (size_t)Z * 4) != hipSuccess) {
+        cleanup();
+        return fail(ASY_ENOMEM, "autotune: allocation of the sample copies failed");
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(ASY_EDEVICE, "autotune: hipEventCreate failed");
+    }
+    std::vector<asy_launch> cands;
+    for (int W : {1, 2, 4}) {
+        if (!net->strat[w_index(W)].ok)
+            continue;
+        asy_launch c{1, 64 * W, 1, 0, net->launch.use_graph, 0};
+        if (validate_launch(net, &c) == ASY_OK)
+            cands.push_back(c);
+    }
+    for (int nt : {128, 256}) {
+        asy_launch c{0, nt, 1, 0, net->launch.use_graph, 0};
+        if (validate_launch(net, &c) == ASY_OK)
+            cands.push_back(c);
+    }
+    g_last_error.clear();
+    const asy_launch saved = net->launch;
+    float best_ms = 0.0f;
+    asy_launch best_c = saved;
+    ZoneArgs za{Z, wY, T, k_zone, t_end, wdt, wacc, wrej, wst, net->queue};
+    asy_status result = ASY_OK;
+    for (const asy_launch &c : cands) {
+        net->launch = c;
+        st = (c.variant == 1) ? ensure_rate_buf(net, Z, nullptr) : ASY_OK;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && st == ASY_OK; ++rep) {  // first run warms up
+            if (hipMemcpy(wY, Y, nY * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
+                hipMemcpy(wdt, dt, (size_t)Z * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
+                hipEventRecord(e0, nullptr) != hipSuccess ||
+                launch_all(net, c, to_dev(o), za, nullptr) != hipSuccess ||
+                hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                st = fail(ASY_EDEVICE, "autotune: a candidate launch failed");
+        }
+        if (st != ASY_OK) {
+            result = st;
+            break;
+        }
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cleanup();
+    net->launch = (result == ASY_OK) ? best_c : saved;
     if (best)
         *best = net->launch;
-    return fail(ASY_ENOTSUP, "autotuning not available in this build");
+    return result;
 }
 
 }  // extern "C"

@@ -1,0 +1,349 @@
+// Variant 1 of the integrator: stratified rows, rates in registers.
+//
+// The creation flux F+_i and the depletion rate k_i of Eq. (eq1.1) are sums
+// over the reactions that create or destroy species i.  Each such sum is a
+// "row" of terms, every term of the form (k_j * Y[x]) * Y[y]:
+//   creation of i by j:          x = first reactant, y = second reactant (or ONE)
+//   depletion of i by j:         x = the other reactant (or ONE),  y = ONE
+// where ONE is an extra LDS cell holding 1.0, so a one-body flux is
+// (k_j * Y_a) * 1.0 and a one-body depletion rate is (k_j * 1.0) * 1.0 --
+// products by 1.0 are exact, and every row is summed from +0.0 in ascending
+// reaction index, exactly as the plain definition does.
+//
+// The host sorts the 2N rows by length and deals them out in strata of
+// 64*W rows, one row per lane.  A lane's column is the concatenation of its
+// rows, each padded to its stratum's length with zero-rate terms (adding +0.0
+// leaves a sum unchanged).  Stratum boundaries are the same slot for every
+// lane, so closing a row is a uniform branch that stores the lane's sum to
+// LDS.  The zone's rates are loaded once into registers (slot s of the lane
+// holds the rate of its term s), so per step the only random LDS traffic is
+// the abundance gathers.  The term descriptors stream from global memory in
+// slot-major order and stay in the L1/L2 caches for all zones.
+#pragma once
+
+#include "integrate_kernels.h"
+
+namespace asynet {
+
+struct StratNetwork {
+    int32_t n_species;
+    int32_t n_reactions;
+    int32_t n_strata;
+    int32_t n_slots;           // slots used (<= compile-time C)
+    const uint32_t *desc;      // [C][lanes]: byte offsets of Y[x] | (of Y[y] << 16) in the zone's LDS block
+    const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
+    const int32_t *strat_end;  // [n_strata]: first slot after each stratum
+    const int32_t *strat_dst;  // [n_strata][lanes]: out cell of the row (F+: i, k: N+i, none: 2N)
+};
+
+// Arrhenius rates of every zone, k[z][j] = A_j exp(-E_j / T_z), once per call.
+// A non-finite T gives NaN rates and T <= 0 gives -1, which the integrator's
+// input checks turn into the zone statuses NONFINITE and BAD_INPUT.
+__global__ void __launch_bounds__(256)
+rates_arrhenius_kernel(int32_t n_zones, int32_t n_reactions, const double *A, const double *E,
+                       const double *T, double *k)
+{
+    const size_t total = (size_t)n_zones * n_reactions;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int z = (int)(idx / n_reactions);
+        const int j = (int)(idx - (size_t)z * n_reactions);
+        const double Tz = T[z];
+        double kj;
+        if (!isfinite(Tz))
+            kj = NAN;
+        else if (!(Tz > 0.0))
+            kj = -1.0;
+        else
+            kj = A[j] * exp(-E[j] / Tz);
+        k[idx] = kj;
+    }
+}
+
+// LDS doubles one zone needs: Y[0..N] (Y[N] = 1.0) and out[0..2N] (out[2N] collects padding rows).
+__host__ __device__ inline int strat_zone_cells(int n_species)
+{
+    const int cells = (n_species + 1) + (2 * n_species + 1);
+    return (cells + 31) / 32 * 32;  // 256-byte aligned zone blocks
+}
+
+template <int W>
+__device__ inline void zone_sync()
+{
+    if constexpr (W == 1) {
+        // one wave: LDS operations of a wave complete in order; this only keeps
+        // the compiler from moving LDS accesses across the phase boundary
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// A workgroup of W waves integrates one zone at a time.
+// Waves per SIMD the register budget allows: the zone's rates take 2*C VGPRs
+// and the pipeline and update about 64 more, out of 512 per SIMD lane.
+template <int C>
+constexpr int strat_waves_per_eu()
+{
+    return 512 / (2 * C + 64) < 1 ? 1 : (512 / (2 * C + 64) > 8 ? 8 : 512 / (2 * C + 64));
+}
+
+template <int W, int SPL, int C>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
+                               amdgpu_waves_per_eu(strat_waves_per_eu<C>())))
+integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates)
+{
+    static_assert(C % 4 == 0, "slots come in blocks of 4");
+    constexpr int LANES = 64 * W;
+    extern __shared__ double lds[];
+    __shared__ double xw_r[W];
+    __shared__ int xw_flag[W];
+    __shared__ int xw_zone;
+
+    const int N = sn.n_species;
+    const int R = sn.n_reactions;
+    const int K = sn.n_strata;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = tid % kWave;
+    const int zl = tid;  // lane within the zone
+    double *Y = lds;
+    double *out = Y + (N + 1);
+
+    for (;;) {
+        // ---- next zone: a wave-wide atomic, lane 0's ticket broadcast by a cross-lane read
+        int z;
+        if constexpr (W == 1) {
+            int ticket = atomicAdd(za.queue, lane == 0 ? 1 : 0);
+            z = __shfl(ticket, 0, kWave);
+        } else {
+            if (wave == 0) {
+                int ticket = atomicAdd(za.queue, lane == 0 ? 1 : 0);
+                ticket = __shfl(ticket, 0, kWave);
+                if (lane == 0)
+                    xw_zone = ticket;
+            }
+            __syncthreads();
+            z = __builtin_amdgcn_readfirstlane(xw_zone);
+            __syncthreads();
+        }
+        if (z >= za.n_zones)
+            break;
+
+        // ---- load the zone: rates into registers (evaluated once per interval), Y into LDS
+        const double t_end = za.t_end[z];
+        const double dt0 = za.dt[z];
+        int flag = 0;  // bit 0: non-finite input, bit 1: out-of-domain input
+        // rates: gathered once per zone from the [zone][reaction] table (the
+        // per-zone input, or the table the Arrhenius rate kernel filled)
+        double kr[C];
+        {
+            const double *kz = rates + (size_t)z * R;
+#pragma unroll
+            for (int s = 0; s < C; ++s) {
+                const int j = sn.rx[s * LANES + zl];
+                double kj = 0.0;
+                if (j >= 0) {
+                    kj = kz[j];
+                    if (!isfinite(kj))
+                        flag |= 1;
+                    else if (kj < 0.0)
+                        flag |= 2;
+                }
+                kr[s] = kj;
+            }
+        }
+        const double *Yz = za.Y + (size_t)z * N;
+#pragma unroll
+        for (int m = 0; m < SPL; ++m) {
+            const int i = zl + m * LANES;
+            if (i < N) {
+                const double y = Yz[i];
+                Y[i] = y;
+                if (!isfinite(y))
+                    flag |= 1;
+                else if (y < 0.0)
+                    flag |= 2;
+            }
+        }
+        if (zl == 0)
+            Y[N] = 1.0;
+        if (!isfinite(t_end) || !isfinite(dt0))
+            flag |= 1;
+        else if (t_end < 0.0 || !(dt0 > 0.0))
+            flag |= 2;
+        flag = wave_or(flag);
+        if constexpr (W > 1) {
+            if (lane == 0)
+                xw_flag[wave] = flag;
+            __syncthreads();
+            flag = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                flag |= xw_flag[w];
+        }
+        zone_sync<W>();
+        if (flag) {
+            if (zl == 0) {
+                za.status[z] = (flag & 1) ? kZoneNonfinite : kZoneBadInput;
+                za.n_acc[z] = 0;
+                za.n_rej[z] = 0;
+            }
+            zone_sync<W>();
+            continue;  // Y and dt stay as given
+        }
+
+        // ---- integrate over [0, t_end]
+        double t = 0.0, step = dt0;
+        int64_t nacc = 0, nrej = 0;
+        int32_t status = kZoneOk;
+        for (;;) {
+            if (t >= t_end) {
+                status = kZoneOk;
+                break;
+            }
+            if (nacc + nrej >= o.max_steps) {
+                status = kZoneMaxSteps;
+                break;
+            }
+            const bool clipped = step >= t_end - t;
+            const double h = clipped ? t_end - t : step;
+
+            // Creation fluxes and depletion rates: one row per lane per stratum.
+            // Strata end on multiples of 4 slots, so the uniform end-of-stratum
+            // branch only separates blocks of 4 slots.  Software pipeline: while
+            // block b is summed, the gathers of block b+1 and the descriptors of
+            // block b+2 are in flight.
+            {
+                int doff = 0;
+                // opaque per step: keeps the descriptor loads, and the addresses
+                // derived from them, inside the step loop instead of in registers
+                asm volatile("" : "+s"(doff));
+                const uint32_t *dsc = sn.desc + doff + zl;
+                const char *Yb = reinterpret_cast<const char *>(Y);
+                constexpr int NB = C / 4;
+                uint32_t dq[C];
+                double gx[C], gy[C];
+#pragma unroll
+                for (int s = 0; s < 8 && s < C; ++s)
+                    dq[s] = dsc[s * LANES];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xffffu));
+                    gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
+                }
+                double acc = 0.0;
+                int k = 0;
+                int next_end = sn.strat_end[0];
+                int dst = sn.strat_dst[zl];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                    for (int s = 4 * (b + 2); s < 4 * (b + 3) && s < C; ++s)
+                        dq[s] = dsc[s * LANES];
+#pragma unroll
+                    for (int s = 4 * (b + 1); s < 4 * (b + 2) && s < C; ++s) {
+                        gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xffffu));
+                        gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
+                    }
+#pragma unroll
+                    for (int s = 4 * b; s < 4 * b + 4; ++s)
+                        acc = acc + (kr[s] * gx[s]) * gy[s];
+                    if (4 * b + 4 == next_end) {
+                        out[dst] = acc;
+                        acc = 0.0;
+                        ++k;
+                        if (k < K) {
+                            next_end = sn.strat_end[k];
+                            dst = sn.strat_dst[k * LANES + zl];
+                        } else {
+                            next_end = C + 1;
+                        }
+                    }
+                }
+            }
+            zone_sync<W>();
+
+            // kappa-switched update of the lane's species and the change measure
+            double yn[SPL];
+            double rloc = 0.0;
+            bool bad = false;
+#pragma unroll
+            for (int m = 0; m < SPL; ++m) {
+                const int i = zl + m * LANES;
+                yn[m] = 0.0;
+                if (i < N) {
+                    const double fp = out[i];
+                    const double kd = out[N + i];
+                    const double y = Y[i];
+                    const double kh = kd * h;
+                    double v;
+                    if (kh < o.kappa)
+                        v = y + h * (fp - kd * y);     // forward Euler
+                    else
+                        v = (y + h * fp) / (1.0 + kh);  // asymptotic form
+                    yn[m] = v;
+                    if (!isfinite(v))
+                        bad = true;
+                    else
+                        rloc = fmax(rloc, fabs(v - y) / fmax(y, o.y_floor));
+                }
+            }
+            if (bad)
+                rloc = INFINITY;
+            double r = wave_max(rloc);
+            if constexpr (W > 1) {
+                if (lane == 0)
+                    xw_r[wave] = r;
+                __syncthreads();
+                r = xw_r[0];
+#pragma unroll
+                for (int w = 1; w < W; ++w)
+                    r = fmax(r, xw_r[w]);
+            }
+            if (r <= o.tol) {
+#pragma unroll
+                for (int m = 0; m < SPL; ++m) {
+                    const int i = zl + m * LANES;
+                    if (i < N)
+                        Y[i] = yn[m];
+                }
+                ++nacc;
+                t = clipped ? t_end : t + h;
+                if (!clipped) {
+                    const double g = (r == 0.0) ? o.grow_max : fmin(o.grow_max, o.safety * o.tol / r);
+                    step = h * g;
+                }
+            } else {
+                ++nrej;
+                const double s = isinf(r) ? o.shrink_min : fmax(o.shrink_min, o.safety * o.tol / r);
+                step = h * s;
+                if (step < o.dt_min) {
+                    status = kZoneDtUnderflow;
+                    break;
+                }
+            }
+            zone_sync<W>();
+        }
+        zone_sync<W>();
+        double *Yo = za.Y + (size_t)z * N;
+#pragma unroll
+        for (int m = 0; m < SPL; ++m) {
+            const int i = zl + m * LANES;
+            if (i < N)
+                Yo[i] = Y[i];
+        }
+        if (zl == 0) {
+            za.dt[z] = step;
+            za.n_acc[z] = nacc;
+            za.n_rej[z] = nrej;
+            za.status[z] = status;
+        }
+        // convergent point between the lane-0 stores and the next zone fetch
+        zone_sync<W>();
+    }
+}
+
+}  // namespace asynet

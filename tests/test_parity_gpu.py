@@ -119,22 +119,63 @@ def test_arrhenius_small_batch_all_zones():
 
 
 LAUNCHES = [
-    dict(threads_per_zone=64, groups_per_cu=0),
-    dict(threads_per_zone=128, groups_per_cu=1),
-    dict(threads_per_zone=256, groups_per_cu=2),
-    dict(threads_per_zone=512, groups_per_cu=0),
+    dict(variant=0, threads_per_zone=64, zones_per_group=1, groups_per_cu=0),
+    dict(variant=0, threads_per_zone=128, zones_per_group=1, groups_per_cu=1),
+    dict(variant=0, threads_per_zone=512, zones_per_group=1, groups_per_cu=0),
+    dict(variant=1, threads_per_zone=64, zones_per_group=1, groups_per_cu=0),
+    dict(variant=1, threads_per_zone=128, zones_per_group=1, groups_per_cu=2),
+    dict(variant=1, threads_per_zone=256, zones_per_group=1, groups_per_cu=0),
+    dict(variant=1, threads_per_zone=128, zones_per_group=1, groups_per_cu=0, use_graph=1),
 ]
 
 
-def test_placement_invariance_and_determinism():
-    """Launch configuration changes only the speed: results are bit-identical."""
-    wl = workloads.preset("n150_r1604_const", n_zones=24)
-    say("case placement n150_r1604_const zones=24")
+@pytest.mark.parametrize("name", ["n150_r1604_const", "n150_r1604_arrhenius"])
+def test_placement_invariance_and_determinism(name):
+    """Kernel variant and launch configuration change only the speed: results are bit-identical."""
+    wl = workloads.preset(name, n_zones=24)
+    say(f"case placement {name} zones=24")
     outs = [run_gpu(wl, launch=c) for c in LAUNCHES]
-    outs.append(run_gpu(wl, launch=LAUNCHES[0]))
+    outs.append(run_gpu(wl, launch=LAUNCHES[3]))
     for o in outs[1:]:
         for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
             np.testing.assert_array_equal(o[key], outs[0][key])
+
+
+def test_graph_replay_repeats_and_autotune():
+    """A captured graph replayed several times, with eager calls in between, matches eager runs;
+    the autotuner returns a configuration that runs and gives the same results."""
+    import torch
+
+    wl = workloads.preset("n150_r1604_arrhenius", n_zones=40)
+    say("case graph replay and autotune")
+    eager = run_gpu(wl)
+    net = binding.Network(wl.network)
+    try:
+        net.set_launch(use_graph=1)
+        buf = net.zone_buffers(wl.zones)
+        Y0, dt0 = buf["Y"].clone(), buf["dt"].clone()
+        for rep in range(3):
+            buf["Y"].copy_(Y0)
+            buf["dt"].copy_(dt0)
+            net.integrate(buf)
+            torch.cuda.synchronize()
+            for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
+                np.testing.assert_array_equal(buf[key].cpu().numpy(), eager[key])
+            z = torch.zeros(1000, device="cuda").sum()   # eager work between replays
+            torch.cuda.synchronize()
+            assert float(z) == 0.0
+        best = binding.asy_autotune(net.handle, net.n_species, net.n_reactions, Y0, buf["t_end"], dt0,
+                                    T=buf["T"], sample_zones=40)
+        say(f"autotuned: {best.as_dict()}")
+        assert net.get_launch() == best.as_dict()
+        buf["Y"].copy_(Y0)
+        buf["dt"].copy_(dt0)
+        net.integrate(buf)
+        torch.cuda.synchronize()
+        for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
+            np.testing.assert_array_equal(buf[key].cpu().numpy(), eager[key])
+    finally:
+        net.close()
 
 
 def test_edge_cases_statuses():
