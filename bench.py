@@ -55,6 +55,8 @@ def main(argv=None):
     ap.add_argument("--launch", default=None, help="JSON dict of asy_launch fields")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch configurations on the workload first")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -68,6 +70,16 @@ def main(argv=None):
     from paper_1409_5826_amd import binding, workloads
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "launches": 3}), flush=True)
+        return 0
     wl = workloads.preset(args.workload, n_zones=args.zones)
     net = binding.Network(wl.network)
     if args.launch:

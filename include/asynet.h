@@ -125,7 +125,9 @@ typedef struct {
     int32_t zones_per_group;  /* zones resident in one workgroup */
     int32_t groups_per_cu;    /* persistent workgroups launched per compute unit; 0 = one per zone */
     int32_t use_graph;        /* 1: replay a captured hipGraph for repeated identical calls */
-    int32_t reserved;         /* must be 0 */
+    int32_t zone_order;       /* 0: zones start in index order; 1: longest first, by the sum of
+                                 their rate constants (variant 1 only).  Scheduling only: the
+                                 results do not depend on it */
 } asy_launch;
 
 /* Fill *o with the defaults listed above.  o: host, non-NULL. */

@@ -78,11 +78,11 @@ class asy_launch(C.Structure):
         ("zones_per_group", C.c_int32),
         ("groups_per_cu", C.c_int32),
         ("use_graph", C.c_int32),
-        ("reserved", C.c_int32),
+        ("zone_order", C.c_int32),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None

@@ -64,6 +64,9 @@ struct asy_network {
     StratLayout strat[3];       // variant 1 with W = 1, 2, 4
     double *rate_buf = nullptr; // Arrhenius rates of one call, [zones][reactions]
     size_t rate_buf_zones = 0;
+    float *key_buf = nullptr;   // scheduling keys of one call, [zones]
+    int32_t *order_buf = nullptr; // scheduling order of one call, [zones]
+    size_t order_buf_zones = 0;
     asy_launch launch{};
     hipStream_t capture_stream = nullptr;
     GraphCache graph;
@@ -73,7 +76,7 @@ namespace {
 
 // ---- variant 1 kernel instances -----------------------------------------------------------
 
-using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *);
+using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *, const int32_t *);
 
 struct StratInstance {
     int W, SPL, C;
@@ -157,8 +160,8 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L.C_needed = slot;
     L.SPL = (N + lanes - 1) / lanes;
     const StratInstance *inst = find_strat_instance(W, L.SPL, L.C_needed);
-    if (!inst)
-        return;
+    if (!inst || L.C_needed > 256)
+        return;  // end_mask holds at most 64 blocks of 4 slots
     const int C = inst->C;
     L.C = C;
     // descriptors hold byte offsets of the two Y cells (cell N = 1.0)
@@ -211,6 +214,9 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L.sn.n_reactions = net->n_reactions;
     L.sn.n_strata = K;
     L.sn.n_slots = L.C_needed;
+    L.sn.end_mask = 0;
+    for (int k = 0; k < K; ++k)
+        L.sn.end_mask |= 1ull << (strat_end[k] / 4 - 1);
     L.sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc);
     L.sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
     L.sn.strat_end = reinterpret_cast<const int32_t *>(base + o_end);
@@ -230,8 +236,10 @@ size_t lds_bytes_variant1(const asy_network *net, int zones_per_group)
 
 asy_status validate_launch(const asy_network *net, const asy_launch *c)
 {
-    if (c->reserved != 0)
-        return fail(ASY_EINVAL, "asy_launch.reserved must be 0");
+    if (c->zone_order != 0 && c->zone_order != 1)
+        return fail(ASY_EINVAL, "asy_launch.zone_order must be 0 or 1");
+    if (c->zone_order == 1 && c->variant != 1)
+        return fail(ASY_EINVAL, "asy_launch.zone_order 1 needs variant 1");
     if (c->groups_per_cu < 0 || c->groups_per_cu > 32)
         return fail(ASY_EINVAL, "asy_launch.groups_per_cu must be in [0, 32]");
     if (c->use_graph != 0 && c->use_graph != 1)
@@ -294,13 +302,30 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
                 return e;
             rates = net->rate_buf;
         }
+        const int32_t *order = nullptr;
+        if (c.zone_order == 1) {
+            const int kb = (int)std::min<size_t>(((size_t)za.n_zones * kWave + 255) / 256,
+                                                 (size_t)net->n_cu * 16);
+            hipLaunchKernelGGL(zone_cost_kernel, dim3(kb), dim3(256), 0, s, za.n_zones,
+                               net->n_reactions, rates, net->key_buf);
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+            const int ob = (za.n_zones + kOrderChunk - 1) / kOrderChunk;
+            hipLaunchKernelGGL(zone_order_kernel, dim3(ob), dim3(1024), 0, s, za.n_zones,
+                               net->key_buf, net->order_buf);
+            e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+            order = net->order_buf;
+        }
         const StratInstance *inst = find_strat_instance(W, L.SPL, L.C);
         const int zpg = c.zones_per_group;
         int grid = (za.n_zones + zpg - 1) / zpg;
         if (c.groups_per_cu > 0)
             grid = std::min(grid, c.groups_per_cu * net->n_cu);
         hipLaunchKernelGGL(inst->fn, dim3(grid), dim3(c.threads_per_zone * zpg),
-                           lds_bytes_variant1(net, zpg), s, L.sn, o, za, rates);
+                           lds_bytes_variant1(net, zpg), s, L.sn, o, za, rates, order);
         return hipGetLastError();
     }
     int grid = za.n_zones;
@@ -347,24 +372,44 @@ asy_status validate_options(const asy_options *o)
     return ASY_OK;
 }
 
-// Make the Arrhenius rate table large enough for n_zones (synchronizes the
-// stream before replacing a table a queued call may still read).
-asy_status ensure_rate_buf(asy_network *net, int32_t n_zones, hipStream_t s)
+// Make the per-call device tables (Arrhenius rates, scheduling keys and
+// order) large enough for n_zones.  Synchronizes the stream before replacing
+// tables a queued call may still read, and drops a captured graph that holds
+// their old addresses.
+asy_status ensure_call_bufs(asy_network *net, const asy_launch &c, int32_t n_zones, hipStream_t s)
 {
-    if (net->rate_form != ASY_RATES_ARRHENIUS || net->rate_buf_zones >= (size_t)n_zones)
+    const bool need_rates = c.variant == 1 && net->rate_form == ASY_RATES_ARRHENIUS &&
+                            net->rate_buf_zones < (size_t)n_zones;
+    const bool need_order = c.variant == 1 && c.zone_order == 1 &&
+                            net->order_buf_zones < (size_t)n_zones;
+    if (!need_rates && !need_order)
         return ASY_OK;
     HIP_TRY(hipStreamSynchronize(s));
-    if (net->graph.exec) {  // a captured graph holds the old table's address
+    if (net->graph.exec) {
         HIP_TRY(hipGraphExecDestroy(net->graph.exec));
         net->graph.exec = nullptr;
         net->graph.key.clear();
     }
-    if (net->rate_buf)
-        HIP_TRY(hipFree(net->rate_buf));
-    net->rate_buf = nullptr;
-    net->rate_buf_zones = 0;
-    HIP_TRY(hipMalloc(&net->rate_buf, sizeof(double) * (size_t)n_zones * net->n_reactions));
-    net->rate_buf_zones = (size_t)n_zones;
+    if (need_rates) {
+        if (net->rate_buf)
+            HIP_TRY(hipFree(net->rate_buf));
+        net->rate_buf = nullptr;
+        net->rate_buf_zones = 0;
+        HIP_TRY(hipMalloc(&net->rate_buf, sizeof(double) * (size_t)n_zones * net->n_reactions));
+        net->rate_buf_zones = (size_t)n_zones;
+    }
+    if (need_order) {
+        if (net->key_buf)
+            HIP_TRY(hipFree(net->key_buf));
+        if (net->order_buf)
+            HIP_TRY(hipFree(net->order_buf));
+        net->key_buf = nullptr;
+        net->order_buf = nullptr;
+        net->order_buf_zones = 0;
+        HIP_TRY(hipMalloc(&net->key_buf, sizeof(float) * (size_t)n_zones));
+        HIP_TRY(hipMalloc(&net->order_buf, sizeof(int32_t) * (size_t)n_zones));
+        net->order_buf_zones = (size_t)n_zones;
+    }
     return ASY_OK;
 }
 
@@ -611,17 +656,22 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
         for (int W : {1, 2, 4})
             build_strat(net, W, rows);
     }
-    // default launch: variant 1 with the fewest waves per zone that has an
-    // instance, else the generic variant 0
+    // default launch: variant 1 with the fewest waves per zone whose rates fit
+    // in 80 slots per lane (two waves per SIMD), else the fewest waves with
+    // any instance, else the generic variant 0 (asy_autotune measures instead)
     asy_launch c{};
     c.variant = 0;
     c.threads_per_zone = N <= 64 ? 64 : (N <= 128 ? 128 : 256);
     c.zones_per_group = 1;
-    for (int W : {1, 2, 4}) {
-        if (net->strat[w_index(W)].ok) {
-            c.variant = 1;
-            c.threads_per_zone = 64 * W;
-            break;
+    for (int pass = 0; pass < 2 && c.variant == 0; ++pass) {
+        for (int W : {1, 2, 4}) {
+            const StratLayout &L = net->strat[w_index(W)];
+            if (L.ok && (pass == 1 || L.C <= 80)) {
+                c.variant = 1;
+                c.threads_per_zone = 64 * W;
+                c.zone_order = 1;
+                break;
+            }
         }
     }
     net->launch = c;
@@ -649,6 +699,10 @@ void asy_network_destroy(asy_network *net)
             (void)hipFree(L.dev);
     if (net->rate_buf)
         (void)hipFree(net->rate_buf);
+    if (net->key_buf)
+        (void)hipFree(net->key_buf);
+    if (net->order_buf)
+        (void)hipFree(net->order_buf);
     delete net;
 }
 
@@ -701,11 +755,9 @@ asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_
     ZoneArgs za{n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected, zone_status, net->queue};
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(net->device));
-    if (net->launch.variant == 1) {
-        st = ensure_rate_buf(net, n_zones, s);
-        if (st != ASY_OK)
-            return st;
-    }
+    st = ensure_call_bufs(net, net->launch, n_zones, s);
+    if (st != ASY_OK)
+        return st;
     return enqueue(net, net->launch, to_dev(o), za, s);
 }
 
@@ -775,7 +827,7 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
     asy_status result = ASY_OK;
     for (const asy_launch &c : cands) {
         net->launch = c;
-        st = (c.variant == 1) ? ensure_rate_buf(net, Z, nullptr) : ASY_OK;
+        st = ensure_call_bufs(net, c, Z, nullptr);
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && st == ASY_OK; ++rep) {  // first run warms up
             if (hipMemcpy(wY, Y, nY * 8, hipMemcpyDeviceToDevice) != hipSuccess ||

@@ -74,6 +74,33 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
+// Maximum over the 64 lanes of a wave through DPP lane moves (no LDS round
+// trips): row_shr 1, 2, 4, 8 leave each row's maximum in its lane 15,
+// row_bcast15 and row_bcast31 carry it across rows into lane 63, which is
+// read back as a uniform value.  Lanes without a DPP source keep their own
+// value, the identity of max.
+#define ASY_DPP_MAX_STEP(v, ctrl, rmask)                                                       \
+    do {                                                                                       \
+        const int lo_ = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v),      \
+                                                    ctrl, rmask, 0xf, false);                  \
+        const int hi_ = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v),      \
+                                                    ctrl, rmask, 0xf, false);                  \
+        v = fmax(v, __hiloint2double(hi_, lo_));                                               \
+    } while (0)
+
+__device__ inline double wave_max_dpp(double v)
+{
+    ASY_DPP_MAX_STEP(v, 0x111, 0xf);  // row_shr:1
+    ASY_DPP_MAX_STEP(v, 0x112, 0xf);  // row_shr:2
+    ASY_DPP_MAX_STEP(v, 0x114, 0xf);  // row_shr:4
+    ASY_DPP_MAX_STEP(v, 0x118, 0xf);  // row_shr:8
+    ASY_DPP_MAX_STEP(v, 0x142, 0xa);  // row_bcast:15 into rows 1 and 3
+    ASY_DPP_MAX_STEP(v, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ inline int wave_or(int v)
 {
 #pragma unroll

@@ -30,6 +30,7 @@ struct StratNetwork {
     int32_t n_reactions;
     int32_t n_strata;
     int32_t n_slots;           // slots used (<= compile-time C)
+    uint64_t end_mask;         // bit b: a stratum ends after block b (slots 4b..4b+3)
     const uint32_t *desc;      // [C][lanes]: byte offsets of Y[x] | (of Y[y] << 16) in the zone's LDS block
     const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
     const int32_t *strat_end;  // [n_strata]: first slot after each stratum
@@ -60,6 +61,74 @@ rates_arrhenius_kernel(int32_t n_zones, int32_t n_reactions, const double *A, co
     }
 }
 
+// Scheduling key of each zone: the sum of its rate constants (for Arrhenius
+// rates it grows with T, and step counts grow with it).  One wave per zone.
+// Non-finite or negative sums (zones that fail their input checks) get key 0.
+__global__ void __launch_bounds__(256)
+zone_cost_kernel(int32_t n_zones, int32_t n_reactions, const double *rates, float *key)
+{
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int n_waves = gridDim.x * blockDim.x / kWave;
+    for (int z = wave; z < n_zones; z += n_waves) {
+        const double *kz = rates + (size_t)z * n_reactions;
+        double s = 0.0;
+        for (int j = lane; j < n_reactions; j += kWave)
+            s += kz[j];
+        for (int off = kWave / 2; off > 0; off >>= 1)
+            s += __shfl_xor(s, off, kWave);
+        if (lane == 0)
+            key[z] = (isfinite(s) && s > 0.0) ? (float)s : 0.0f;
+    }
+}
+
+// Longest-first scheduling order: each workgroup sorts one chunk of up to
+// kOrderChunk zones by descending key (bitonic sort in LDS on key bits | zone
+// index; keys are non-negative floats, whose bit patterns order like the
+// values) and writes the chunk's zone indices in that order.
+constexpr int kOrderChunk = 16384;
+
+__global__ void __launch_bounds__(1024)
+zone_order_kernel(int32_t n_zones, const float *key, int32_t *order)
+{
+    __shared__ unsigned long long v[kOrderChunk];
+    const int base = blockIdx.x * kOrderChunk;
+    const int n = min(kOrderChunk, n_zones - base);
+    int pow2 = 1;
+    while (pow2 < n)
+        pow2 <<= 1;
+    for (int i = threadIdx.x; i < pow2; i += blockDim.x) {
+        unsigned long long e = 0;  // padding sorts last (key 0, descending order)
+        if (i < n) {
+            const unsigned int kb = __float_as_uint(key[base + i]);
+            // descending key, then ascending zone index: sort ascending on (~key, index)
+            e = ((unsigned long long)(~kb) << 32) | (unsigned int)(base + i);
+        } else {
+            e = ~0ull;
+        }
+        v[i] = e;
+    }
+    __syncthreads();
+    for (int size = 2; size <= pow2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < pow2; i += blockDim.x) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = v[i], b = v[j];
+                    if ((a > b) == up) {
+                        v[i] = b;
+                        v[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        order[base + i] = (int32_t)(v[i] & 0xffffffffu);
+}
+
 // LDS doubles one zone needs: Y[0..N] (Y[N] = 1.0) and out[0..2N] (out[2N] collects padding rows).
 __host__ __device__ inline int strat_zone_cells(int n_species)
 {
@@ -82,18 +151,20 @@ __device__ inline void zone_sync()
 }
 
 // A workgroup of W waves integrates one zone at a time.
-// Waves per SIMD the register budget allows: the zone's rates take 2*C VGPRs
-// and the pipeline and update about 64 more, out of 512 per SIMD lane.
+// Waves per SIMD the register budget allows: the zone's rates take 2*C
+// registers and the pipelines, addresses and update about 128 more, out of
+// 512 per SIMD lane.
 template <int C>
 constexpr int strat_waves_per_eu()
 {
-    return 512 / (2 * C + 64) < 1 ? 1 : (512 / (2 * C + 64) > 8 ? 8 : 512 / (2 * C + 64));
+    return 512 / (2 * C + 128) < 1 ? 1 : (512 / (2 * C + 128) > 8 ? 8 : 512 / (2 * C + 128));
 }
 
-template <int W, int SPL, int C>
+template <int W, int SPL, int C, int GA = 2>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
                                amdgpu_waves_per_eu(strat_waves_per_eu<C>())))
-integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates)
+integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates,
+                       const int32_t *order)
 {
     static_assert(C % 4 == 0, "slots come in blocks of 4");
     constexpr int LANES = 64 * W;
@@ -131,6 +202,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         }
         if (z >= za.n_zones)
             break;
+        if (order)  // tickets walk the zones in the scheduling order
+            z = __builtin_amdgcn_readfirstlane(order[z]);
 
         // ---- load the zone: rates into registers (evaluated once per interval), Y into LDS
         const double t_end = za.t_end[z];
@@ -199,6 +272,29 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         double t = 0.0, step = dt0;
         int64_t nacc = 0, nrej = 0;
         int32_t status = kZoneOk;
+        const uint64_t emask = sn.end_mask;
+        constexpr int NB = C / 4;
+        // the lane's row of every stratum (at most 2*SPL strata), kept in registers
+        constexpr int KMAX = 2 * SPL;
+        int dst_zone[KMAX];
+#pragma unroll
+        for (int m = 0; m < KMAX; ++m)
+            dst_zone[m] = (m < K) ? sn.strat_dst[m * LANES + zl] : 2 * N;
+        constexpr int kDescAhead = 4;    // descriptor prefetch distance, in blocks of 4 slots
+        constexpr int kGatherAhead = GA; // abundance-gather distance, in blocks
+        const char *Yb = reinterpret_cast<const char *>(Y);
+        uint32_t dq[C];
+        const uint32_t *dsc;
+        {
+            int doff = 0;
+            // opaque offset: the descriptor loads stay inside the step loop
+            // instead of being hoisted into registers for the whole zone
+            asm volatile("" : "+s"(doff));
+            dsc = sn.desc + doff + zl;
+#pragma unroll
+            for (int s = 0; s < 4 * kDescAhead && s < C; ++s)
+                dq[s] = dsc[s * LANES];
+        }
         for (;;) {
             if (t >= t_end) {
                 status = kZoneOk;
@@ -212,57 +308,56 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             const double h = clipped ? t_end - t : step;
 
             // Creation fluxes and depletion rates: one row per lane per stratum.
-            // Strata end on multiples of 4 slots, so the uniform end-of-stratum
-            // branch only separates blocks of 4 slots.  Software pipeline: while
-            // block b is summed, the gathers of block b+1 and the descriptors of
-            // block b+2 are in flight.
+            // Strata end on multiples of 4 slots; the blocks that close a
+            // stratum are flagged in end_mask, a uniform kernel argument, so
+            // closing a row is a scalar bit test on a compile-time block index.
+            // Software pipeline: while block b is summed, the gathers of blocks
+            // up to b+kGatherAhead and the descriptors of block b+kDescAhead are
+            // in flight; the
+            // first kDescAhead blocks' descriptors of a step are loaded during
+            // the previous step's update.
             {
-                int doff = 0;
-                // opaque per step: keeps the descriptor loads, and the addresses
-                // derived from them, inside the step loop instead of in registers
-                asm volatile("" : "+s"(doff));
-                const uint32_t *dsc = sn.desc + doff + zl;
-                const char *Yb = reinterpret_cast<const char *>(Y);
-                constexpr int NB = C / 4;
-                uint32_t dq[C];
                 double gx[C], gy[C];
 #pragma unroll
-                for (int s = 0; s < 8 && s < C; ++s)
-                    dq[s] = dsc[s * LANES];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
+                for (int s = 0; s < 4 * kGatherAhead && s < C; ++s) {
                     gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xffffu));
                     gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
                 }
                 double acc = 0.0;
-                int k = 0;
-                int next_end = sn.strat_end[0];
-                int dst = sn.strat_dst[zl];
+                int dq_dst[KMAX];
+#pragma unroll
+                for (int m = 0; m < KMAX; ++m)
+                    dq_dst[m] = dst_zone[m];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
 #pragma unroll
-                    for (int s = 4 * (b + 2); s < 4 * (b + 3) && s < C; ++s)
+                    for (int s = 4 * (b + kDescAhead); s < 4 * (b + kDescAhead + 1) && s < C; ++s)
                         dq[s] = dsc[s * LANES];
 #pragma unroll
-                    for (int s = 4 * (b + 1); s < 4 * (b + 2) && s < C; ++s) {
+                    for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s) {
                         gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xffffu));
                         gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
                     }
 #pragma unroll
                     for (int s = 4 * b; s < 4 * b + 4; ++s)
                         acc = acc + (kr[s] * gx[s]) * gy[s];
-                    if (4 * b + 4 == next_end) {
-                        out[dst] = acc;
+                    if ((emask >> b) & 1u) {
+                        out[dq_dst[0]] = acc;
                         acc = 0.0;
-                        ++k;
-                        if (k < K) {
-                            next_end = sn.strat_end[k];
-                            dst = sn.strat_dst[k * LANES + zl];
-                        } else {
-                            next_end = C + 1;
-                        }
+#pragma unroll
+                        for (int m = 0; m + 1 < KMAX; ++m)
+                            dq_dst[m] = dq_dst[m + 1];
                     }
                 }
+            }
+            // descriptors of the first blocks of the next step
+            {
+                int doff = 0;
+                asm volatile("" : "+s"(doff));
+                dsc = sn.desc + doff + zl;
+#pragma unroll
+                for (int s = 0; s < 4 * kDescAhead && s < C; ++s)
+                    dq[s] = dsc[s * LANES];
             }
             zone_sync<W>();
 
@@ -293,7 +388,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             }
             if (bad)
                 rloc = INFINITY;
-            double r = wave_max(rloc);
+            double r = wave_max_dpp(rloc);
             if constexpr (W > 1) {
                 if (lane == 0)
                     xw_r[wave] = r;

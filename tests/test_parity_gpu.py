@@ -119,13 +119,14 @@ def test_arrhenius_small_batch_all_zones():
 
 
 LAUNCHES = [
-    dict(variant=0, threads_per_zone=64, zones_per_group=1, groups_per_cu=0),
-    dict(variant=0, threads_per_zone=128, zones_per_group=1, groups_per_cu=1),
-    dict(variant=0, threads_per_zone=512, zones_per_group=1, groups_per_cu=0),
-    dict(variant=1, threads_per_zone=64, zones_per_group=1, groups_per_cu=0),
-    dict(variant=1, threads_per_zone=128, zones_per_group=1, groups_per_cu=2),
-    dict(variant=1, threads_per_zone=256, zones_per_group=1, groups_per_cu=0),
-    dict(variant=1, threads_per_zone=128, zones_per_group=1, groups_per_cu=0, use_graph=1),
+    dict(variant=0, threads_per_zone=64, zones_per_group=1, groups_per_cu=0, zone_order=0),
+    dict(variant=0, threads_per_zone=128, zones_per_group=1, groups_per_cu=1, zone_order=0),
+    dict(variant=0, threads_per_zone=512, zones_per_group=1, groups_per_cu=0, zone_order=0),
+    dict(variant=1, threads_per_zone=64, zones_per_group=1, groups_per_cu=0, zone_order=1),
+    dict(variant=1, threads_per_zone=128, zones_per_group=1, groups_per_cu=2, zone_order=0),
+    dict(variant=1, threads_per_zone=256, zones_per_group=1, groups_per_cu=0, zone_order=1),
+    dict(variant=1, threads_per_zone=128, zones_per_group=1, groups_per_cu=0, use_graph=1,
+         zone_order=1),
 ]
 
 
