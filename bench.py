@@ -31,6 +31,40 @@ LDS_BYTES_PER_CLK_CU = 128
 LDS_PEAK_GBS = N_CU * LDS_BYTES_PER_CLK_CU * CLOCK_HZ / 1e9
 
 
+def kernel_source_sha256() -> str:
+    """Hash of the HIP sources, to tie a profile summary to the kernel it measured."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1409_5826_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 summary of this workload
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size), or None
+    when there is no summary or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"integrate_strat_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("|", "*", "#", "`")):
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def algorithmic_bytes_per_zone_step(n_species: int, n_reactions: int, n_destruction: int) -> int:
     """LDS bytes one attempted step of one zone must move (FP64 = 8 B, index = 2 B).
 
@@ -179,8 +213,9 @@ def main(argv=None):
             "peak": LDS_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / LDS_PEAK_GBS,
-            "traffic": None,
+            "traffic": profiled_traffic(wl.name),
             "bytes_per_zone_step": b_step,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
         },
         "cpu_baseline": cpu,
     }
