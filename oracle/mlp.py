@@ -1,0 +1,148 @@
+"""CPU reference of the learned step-size proposer (test infrastructure only).
+
+A multilayer perceptron 166 -> 128 -> 128 -> 1 with ReLU hidden layers maps
+features of a zone's accepted state to o, the predicted log2 of the ratio of
+the next accepted step to the last one.  The paper has no learned
+controller; this network, its features and its training follow the
+specification of the learned-timestep form of this build (see the design
+notes), in plain numpy FP64 with BF16 rounding applied at exactly the points
+where the GPU kernels feed their matrix cores:
+
+  forward   xb = bf16(x), W*b = bf16(W*)
+            a1 = xb W1b + b1,  h1b = bf16(relu(a1))
+            a2 = h1b W2b + b2, h2b = bf16(relu(a2))
+            o  = h2b W3b + b3
+  loss      L = mean_b (o_b - y_b)^2
+  backward  g_o = 2 (o - y) / B,             g_ob = bf16(g_o)
+            dW3 = h2b^T g_ob,                db3 = sum g_o
+            g_a2 = (g_ob W3b^T) * [a2 > 0],  g_a2b = bf16(g_a2)
+            dW2 = h1b^T g_a2b,               db2 = sum_b g_a2
+            g_a1 = (g_a2b W2b^T) * [a1 > 0], g_a1b = bf16(g_a1)
+            dW1 = xb^T g_a1b,                db1 = sum_b g_a1
+  Adam      m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+            W -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+
+Weights are kept as FP32 masters; the forward pass uses their BF16 copies.
+Accumulation here is FP64 (the GPU accumulates in FP32, so the two agree to
+accumulation-order rounding).  `bf16=False` switches every rounding off,
+which the finite-difference check of the backward pass uses.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_IN = 166
+N_IN_PAD = 192
+N_HID = 128
+
+# flat parameter layout shared with the C ABI: W1 [192x128], b1 [128], W2 [128x128], b2 [128],
+# W3 [128], b3 [1]  (W1 rows >= 166 multiply zero-padded inputs)
+SIZES = {"W1": N_IN_PAD * N_HID, "b1": N_HID, "W2": N_HID * N_HID, "b2": N_HID, "W3": N_HID, "b3": 1}
+N_PARAMS = sum(SIZES.values())
+
+
+def bf16(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+
+    Rounds the float32 value of x: keep the top 16 bits of the float32 bit
+    pattern after adding 0x7FFF plus the lowest kept bit.
+    """
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, out)
+
+
+def unpack(p: np.ndarray) -> dict:
+    p = np.asarray(p, dtype=np.float64)
+    out, off = {}, 0
+    for name, n in SIZES.items():
+        out[name] = p[off:off + n]
+        off += n
+    out["W1"] = out["W1"].reshape(N_IN_PAD, N_HID)
+    out["W2"] = out["W2"].reshape(N_HID, N_HID)
+    return out
+
+
+def pack(d: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(d[name], dtype=np.float64).ravel() for name in SIZES])
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-uniform hidden layers, small output layer, zero biases (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = np.zeros((N_IN_PAD, N_HID))
+    lim1 = np.sqrt(6.0 / N_IN)
+    W1[:N_IN] = rng.uniform(-lim1, lim1, size=(N_IN, N_HID))
+    lim2 = np.sqrt(6.0 / N_HID)
+    W2 = rng.uniform(-lim2, lim2, size=(N_HID, N_HID))
+    W3 = rng.uniform(-0.01, 0.01, size=N_HID)
+    d = dict(W1=W1, b1=np.zeros(N_HID), W2=W2, b2=np.zeros(N_HID), W3=W3, b3=np.zeros(1))
+    return pack(d).astype(np.float32).astype(np.float64)
+
+
+def _pad(x):
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros((x.shape[0], N_IN_PAD))
+    out[:, :x.shape[1]] = x
+    return out
+
+
+def forward(params, x, bf16_round=True):
+    """o [B] and the cache for backward; x [B, 166] (FP32 features)."""
+    r = bf16 if bf16_round else (lambda v: np.asarray(v, dtype=np.float64))
+    p = unpack(params)
+    xb = r(_pad(x))
+    W1b, W2b, W3b = r(p["W1"]), r(p["W2"]), r(p["W3"])
+    a1 = xb @ W1b + p["b1"]
+    h1b = r(np.maximum(a1, 0.0))
+    a2 = h1b @ W2b + p["b2"]
+    h2b = r(np.maximum(a2, 0.0))
+    o = h2b @ W3b + p["b3"][0]
+    cache = dict(xb=xb, a1=a1, h1b=h1b, a2=a2, h2b=h2b, W1b=W1b, W2b=W2b, W3b=W3b)
+    return o, cache
+
+
+def loss(params, x, y, bf16_round=True) -> float:
+    o, _ = forward(params, x, bf16_round)
+    return float(np.mean((o - np.asarray(y, dtype=np.float64)) ** 2))
+
+
+def backward(params, x, y, bf16_round=True):
+    """(loss, flat gradient) of the mean squared error."""
+    r = bf16 if bf16_round else (lambda v: np.asarray(v, dtype=np.float64))
+    y = np.asarray(y, dtype=np.float64)
+    B = len(y)
+    o, c = forward(params, x, bf16_round)
+    g_o = 2.0 * (o - y) / B
+    g_ob = r(g_o)
+    dW3 = c["h2b"].T @ g_ob
+    db3 = np.array([g_o.sum()])
+    g_a2 = np.outer(g_ob, c["W3b"]) * (c["a2"] > 0)
+    g_a2b = r(g_a2)
+    dW2 = c["h1b"].T @ g_a2b
+    db2 = g_a2.sum(axis=0)
+    g_a1 = (g_a2b @ c["W2b"].T) * (c["a1"] > 0)
+    g_a1b = r(g_a1)
+    dW1 = c["xb"].T @ g_a1b
+    db1 = g_a1.sum(axis=0)
+    grads = pack(dict(W1=dW1, b1=db1, W2=dW2, b2=db2, W3=dW3, b3=db3))
+    return float(np.mean((o - y) ** 2)), grads
+
+
+def adam_step(params, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (t = step number starting at 1); returns (params, m, v)."""
+    m = beta1 * m + (1 - beta1) * grads
+    v = beta2 * v + (1 - beta2) * grads * grads
+    mh = m / (1 - beta1 ** t)
+    vh = v / (1 - beta2 ** t)
+    params = params - lr * mh / (np.sqrt(vh) + eps)
+    return params, m, v
+
+
+def quantize_log2_ratio(o) -> np.ndarray:
+    """The proposal exponent q = round(32 clamp(o, -3, 3)) / 32 as the integer 32 q."""
+    o = np.clip(np.asarray(o, dtype=np.float64), -3.0, 3.0)
+    return np.rint(32.0 * o).astype(np.int64)
