@@ -199,6 +199,85 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
                         const double *Y, const double *T, const double *k_zone,
                         const double *t_end, const double *dt, asy_launch *best);
 
+/*
+ * ---- Learned step proposer ---------------------------------------------------------------
+ * A 166 -> 128 -> 128 -> 1 ReLU perceptron that maps features of a zone's
+ * accepted state to o, the predicted log2 of the ratio of the next accepted
+ * step to the last one (no counterpart in the paper: it only replaces how the
+ * next trial step of the adaptive network timestep is proposed).  Weights are
+ * FP32 masters; every product runs on the matrix cores with BF16 operands and
+ * FP32 accumulation.  Parameters travel as one FP32 vector of
+ * ASY_MLP_N_PARAMS values: W1 [192][128] (input-major; rows 166..191 multiply
+ * zero padding), b1 [128], W2 [128][128], b2 [128], W3 [128], b3 [1].
+ * Features of a state (ASY_MLP_N_IN values): x[i] = max(log10 Y_i, -30)/30
+ * for i < n_species (Y_i <= 0 gives -1), then log10 of the largest and of the
+ * mean of k_i*h, log10 h, log10 tol (each /10, arguments floored at 1e-300),
+ * zero up to ASY_MLP_N_IN; k_i are the depletion rates of the last accepted
+ * step h.  Requires n_species <= ASY_MLP_N_IN - 4.
+ */
+#define ASY_MLP_N_IN 166
+#define ASY_MLP_N_PARAMS 41345
+
+typedef struct asy_mlp asy_mlp; /* opaque training context; owned by the library */
+
+/* Create a context for batches of up to batch_max samples; parameters start at zero. */
+asy_status asy_mlp_create(int32_t batch_max, asy_mlp **out);
+void       asy_mlp_destroy(asy_mlp *m); /* NULL is a no-op */
+
+/* Copy parameters in (host [ASY_MLP_N_PARAMS]; resets the Adam state) or out. */
+asy_status asy_mlp_set_params(asy_mlp *m, const float *params);
+asy_status asy_mlp_get_params(const asy_mlp *m, float *params);
+
+/* o[b] for x [n][ASY_MLP_N_IN] (device FP32); o device [n]; n <= batch_max. */
+asy_status asy_mlp_forward(asy_mlp *m, int32_t n, const float *x, float *o, void *stream);
+
+/* Loss (device [1]) and gradient (device [ASY_MLP_N_PARAMS]) of mean (o - y)^2. */
+asy_status asy_mlp_gradient(asy_mlp *m, int32_t n, const float *x, const float *y, float *loss,
+                            float *grad, void *stream);
+
+/*
+ * One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on the batch
+ * (x, y); loss (device [1], may be NULL) receives the batch loss before the update.
+ */
+asy_status asy_mlp_train_step(asy_mlp *m, int32_t n, const float *x, const float *y, float lr,
+                              float *loss, void *stream);
+
+/*
+ * Batched inference through the same routine the integrator runs per zone
+ * (one wave per sample, weights arranged for the matrix cores); o device [n].
+ */
+asy_status asy_mlp_infer(asy_mlp *m, int32_t n, const float *x, float *o, void *stream);
+
+/* Give a network the current parameters of m for ASY_CTRL_LEARNED (a copy is kept). */
+asy_status asy_set_mlp(asy_network *net, const asy_mlp *m);
+
+/*
+ * With opts->controller == ASY_CTRL_LEARNED, asy_integrate_batch proposes the
+ * step after every accepted, unclipped step h as h * 2^(q/32), where
+ * q = rint(32 clamp(o, -3, 3)) and o is the network's output for the accepted
+ * state; if that attempt is rejected the zone falls back to the plain
+ * proposal, and after any further rejection to the plain shrink rule, until a
+ * step is accepted.  Requires asy_set_mlp (else ASY_ESTATE) and launch variant 1
+ * with a learned kernel instance (else ASY_ENOTSUP).
+ *
+ * asy_integrate_batch_trace: asy_integrate_batch that also writes training
+ * records, one per sampled accepted state of zones z < trace_zones (every
+ * stride-th accepted step), ASY_TRACE_REC floats each, into trace (device
+ * [capacity][ASY_TRACE_REC]): [0, 166) the state's features, [166] the label
+ * log2(h_next / h) of the step accepted next (NaN if the zone ended first or
+ * that step was clipped to t_end), [167] 32 q of the learned proposal (NaN
+ * with the plain controller), [168] zone index, [169] accepted-step index.
+ * count (device, in/out) counts records taken; those beyond capacity are
+ * dropped.  capacity < 2^31.  Record order is not deterministic.
+ */
+#define ASY_TRACE_REC 170
+asy_status asy_integrate_batch_trace(asy_network *net, const asy_options *opts, int32_t n_zones,
+                                     double *Y, const double *T, const double *k_zone,
+                                     const double *t_end, double *dt, int64_t *n_accepted,
+                                     int64_t *n_rejected, int32_t *zone_status, float *trace,
+                                     int64_t capacity, unsigned long long *count, int32_t stride,
+                                     int32_t trace_zones, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *asy_last_error(void);
 

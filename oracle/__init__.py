@@ -76,6 +76,13 @@ def lib():
         L.orc_integrate_batch.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_int32, P, P, P,
                                           P, P, P, P, P, C.POINTER(Options), C.c_int32]
         L.orc_max_threads.restype = C.c_int32
+        L.orc_mlp_forward.argtypes = [P, P]
+        L.orc_mlp_forward.restype = C.c_double
+        L.orc_mlp_features.argtypes = [C.c_int32, P, P, C.c_double, C.c_double, P]
+        L.orc_integrate_zone_learned.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_double, P,
+                                                 C.POINTER(Options), C.c_int32, P, P, C.c_int64,
+                                                 C.POINTER(_LearnLog), P, P]
+        L.orc_integrate_zone_learned.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -95,6 +102,11 @@ def _f64(a):
 class _Trace(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("count", C.c_int64), ("h", C.c_void_p),
                 ("r", C.c_void_p), ("accepted", C.c_void_p)]
+
+
+class _LearnLog(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("count", C.c_int64), ("q", C.c_void_p),
+                ("feat", C.c_void_p), ("label", C.c_void_p), ("n_acc", C.c_void_p)]
 
 
 def rates_arrhenius(A, E, T) -> np.ndarray:
@@ -182,3 +194,54 @@ def integrate_batch(net, zones, opts: Optional[Options] = None, n_threads: int =
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def mlp_forward_c(params, x) -> float:
+    """The C reference's network output for one feature vector (166 floats)."""
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    xv = np.ascontiguousarray(x, dtype=np.float32)
+    return float(lib().orc_mlp_forward(_p(p), _p(xv)))
+
+
+def mlp_features(Y, kd, h, tol) -> np.ndarray:
+    Y, kd = _f64(Y), _f64(kd)
+    x = np.zeros(166, dtype=np.float32)
+    lib().orc_mlp_features(len(Y), _p(Y), _p(kd), float(h), float(tol), _p(x))
+    return x
+
+
+def integrate_zone_learned(net, k, Y0, t_end, dt0, params=None, opts: Optional[Options] = None,
+                           learned=True, q_replay=None, log_capacity=0):
+    """One zone with the learned (or, learned=False, the plain) controller.
+
+    q_replay (optional) supplies the first 32 q values in place of the network.
+    With log_capacity > 0 the result holds, per proposal point, q (None for the
+    plain controller), the features, the label and the accepted-step count.
+    """
+    opts = opts or options()
+    a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
+    k = _f64(k)
+    Y = _f64(Y0).copy()
+    dt = np.array([dt0], dtype=np.float64)
+    if learned and params is None:
+        raise ValueError("the learned controller needs params")
+    p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+    qr = None if q_replay is None else _i32(q_replay)
+    cap = int(log_capacity)
+    lq = np.zeros(max(cap, 1), np.int32)
+    lf = np.zeros((max(cap, 1), 166), np.float32)
+    ll = np.zeros(max(cap, 1), np.float64)
+    ln = np.zeros(max(cap, 1), np.int64)
+    lg = _LearnLog(cap, 0, lq.ctypes.data, lf.ctypes.data, ll.ctypes.data, ln.ctypes.data)
+    na, nr = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    st = lib().orc_integrate_zone_learned(net.n_species, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y),
+                                          float(t_end), _p(dt), C.byref(opts), int(bool(learned)),
+                                          _p(p), _p(qr), 0 if qr is None else len(qr), C.byref(lg),
+                                          _p(na), _p(nr))
+    n = min(int(lg.count), cap)
+    out = dict(Y=Y, dt=float(dt[0]), n_acc=int(na[0]), n_rej=int(nr[0]), status=int(st),
+               n_prop=int(lg.count))
+    if cap:
+        out["log"] = dict(q=lq[:n].copy() if learned else None, feat=lf[:n].copy(),
+                          label=ll[:n].copy(), n_acc=ln[:n].copy())
+    return out

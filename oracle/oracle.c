@@ -266,3 +266,225 @@ int32_t orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Learned step proposer (no counterpart in the paper: it only changes how the next trial
+ * step of the adaptive timestep is proposed).  Network 166 -> 128 -> 128 -> 1 with ReLU,
+ * parameters as one float vector: W1 [192][128], b1 [128], W2 [128][128], b2 [128],
+ * W3 [128], b3 [1].  Operands are rounded to bfloat16 where the device feeds its matrix
+ * cores; sums are FP64 in ascending index.
+ * ------------------------------------------------------------------------------------------ */
+#define ORC_MLP_IN 166
+#define ORC_MLP_IN_PAD 192
+#define ORC_MLP_HID 128
+
+/* round to the nearest bfloat16 (ties to even) of the float32 value of x */
+static double orc_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return NAN;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+double orc_mlp_forward(const float *p, const float *x)
+{
+    const float *W1 = p, *b1 = W1 + ORC_MLP_IN_PAD * ORC_MLP_HID, *W2 = b1 + ORC_MLP_HID;
+    const float *b2 = W2 + ORC_MLP_HID * ORC_MLP_HID, *W3 = b2 + ORC_MLP_HID, *b3 = W3 + ORC_MLP_HID;
+    double h1[ORC_MLP_HID], h2[ORC_MLP_HID];
+    for (int j = 0; j < ORC_MLP_HID; ++j) {
+        double a = 0.0;
+        for (int k = 0; k < ORC_MLP_IN; ++k)
+            a += orc_bf16(x[k]) * orc_bf16(W1[k * ORC_MLP_HID + j]);
+        a += b1[j];
+        h1[j] = orc_bf16(a > 0.0 ? a : 0.0);
+    }
+    for (int j = 0; j < ORC_MLP_HID; ++j) {
+        double a = 0.0;
+        for (int k = 0; k < ORC_MLP_HID; ++k)
+            a += h1[k] * orc_bf16(W2[k * ORC_MLP_HID + j]);
+        a += b2[j];
+        h2[j] = orc_bf16(a > 0.0 ? a : 0.0);
+    }
+    double o = 0.0;
+    for (int k = 0; k < ORC_MLP_HID; ++k)
+        o += h2[k] * orc_bf16(W3[k]);
+    return o + b3[0];
+}
+
+/*
+ * Features of an accepted state Y (after a step of length h whose depletion
+ * rates, evaluated at the state the step started from, are kd):
+ *   x[i] = max(log10 Y_i, -30) / 30 (log10 argument floored at 1e-300),
+ *   x[N] = log10 max_i(kd_i h) / 10, x[N+1] = log10 mean_i(kd_i h) / 10,
+ *   x[N+2] = log10 h / 10, x[N+3] = log10 tol / 10 (arguments floored at 1e-300),
+ *   zero up to 166.  Each value is rounded to float.
+ */
+void orc_mlp_features(int32_t n_species, const double *Y, const double *kd, double h, double tol,
+                      float *x)
+{
+    double kmax = 0.0, ksum = 0.0;
+    for (int i = 0; i < ORC_MLP_IN; ++i)
+        x[i] = 0.0f;
+    for (int32_t i = 0; i < n_species; ++i) {
+        x[i] = (float)(fmax(log10(fmax(Y[i], 1e-300)), -30.0) / 30.0);
+        double kh = kd[i] * h;
+        kmax = fmax(kmax, kh);
+        ksum += kh;
+    }
+    x[n_species] = (float)(log10(fmax(kmax, 1e-300)) / 10.0);
+    x[n_species + 1] = (float)(log10(fmax(ksum / n_species, 1e-300)) / 10.0);
+    x[n_species + 2] = (float)(log10(h) / 10.0);
+    x[n_species + 3] = (float)(log10(tol) / 10.0);
+}
+
+/* What the learned integration logs at each proposal point (an accepted, unclipped step
+ * with t < t_end after it), in the order the points occur. */
+typedef struct {
+    int64_t capacity; /* entries available in the arrays below (any may be NULL) */
+    int64_t count;    /* proposal points met (may exceed capacity) */
+    int32_t *q;       /* 32 q of the proposal (INT32_MIN with the plain controller) */
+    float *feat;      /* [capacity][166] features of the accepted state */
+    double *label;    /* log2(h_next / h) of the next accepted step; NaN if that step was
+                         clipped to t_end or none followed */
+    int64_t *n_acc;   /* accepted steps at the point */
+} orc_learn_log;
+
+/*
+ * One zone with either controller, logging every proposal point.
+ * learned = 0: the plain controller (the log still records features and labels).
+ * learned = 1: after every accepted, unclipped step h with t < t_end the next
+ * attempt is h * 2^(q/32), q = rint(32 clamp(o, -3, 3)) with o the network's
+ * output for the state's features (2^(q/32) = 2^floor(q/32) * 2^((q mod 32)/32),
+ * the second factor from a table of exp2(b/32)); if that attempt is rejected
+ * the plain proposal is tried, and further rejections shrink by the plain rule.
+ * q_replay (optional, n_replay values) supplies 32 q for the first proposals
+ * instead of the network.
+ */
+int32_t orc_integrate_zone_learned(int32_t n_species, int32_t n_reactions, const int32_t *a,
+                                   const int32_t *b, const int32_t *c, const double *k, double *Y,
+                                   double t_end, double *dt, const orc_options *o, int32_t learned,
+                                   const float *mlp, const int32_t *q_replay, int64_t n_replay,
+                                   orc_learn_log *lg, int64_t *n_acc_out, int64_t *n_rej_out)
+{
+    double pow2[32];
+    for (int i = 0; i < 32; ++i)
+        pow2[i] = exp2(i / 32.0);
+    int64_t n_acc = 0, n_rej = 0, n_prop = 0;
+    *n_acc_out = 0;
+    *n_rej_out = 0;
+    if (lg)
+        lg->count = 0;
+    for (int32_t j = 0; j < n_reactions; ++j)
+        if (!isfinite(k[j]))
+            return ORC_ZONE_NONFINITE;
+    for (int32_t i = 0; i < n_species; ++i)
+        if (!isfinite(Y[i]))
+            return ORC_ZONE_NONFINITE;
+    if (!isfinite(t_end) || !isfinite(*dt))
+        return ORC_ZONE_NONFINITE;
+    for (int32_t j = 0; j < n_reactions; ++j)
+        if (k[j] < 0.0)
+            return ORC_ZONE_BAD_INPUT;
+    for (int32_t i = 0; i < n_species; ++i)
+        if (Y[i] < 0.0)
+            return ORC_ZONE_BAD_INPUT;
+    if (t_end < 0.0 || !(*dt > 0.0))
+        return ORC_ZONE_BAD_INPUT;
+
+    double *Fp = malloc(sizeof(double) * (size_t)n_species);
+    double *kd = malloc(sizeof(double) * (size_t)n_species);
+    double *Yn = malloc(sizeof(double) * (size_t)n_species);
+    float x[ORC_MLP_IN];
+    double t = 0.0, step = *dt, plain_step = *dt, h_prev = 0.0;
+    int mlp_attempt = 0;
+    int64_t pending = -1; /* log entry waiting for its label */
+    int32_t status = ORC_ZONE_OK;
+    for (;;) {
+        if (t >= t_end) {
+            status = ORC_ZONE_OK;
+            break;
+        }
+        if (n_acc + n_rej >= o->max_steps) {
+            status = ORC_ZONE_MAX_STEPS;
+            break;
+        }
+        int clipped = step >= t_end - t;
+        double h = clipped ? t_end - t : step;
+        orc_rhs(n_species, n_reactions, a, b, c, k, Y, Fp, kd);
+        orc_update(n_species, Y, Fp, kd, h, o->kappa, Yn, NULL);
+        double r = orc_change(n_species, Y, Yn, o->y_floor);
+        if (r <= o->tol) {
+            memcpy(Y, Yn, sizeof(double) * (size_t)n_species);
+            n_acc++;
+            t = clipped ? t_end : t + h;
+            mlp_attempt = 0;
+            if (pending >= 0 && lg->label)
+                lg->label[pending] = clipped ? NAN : log2(h / h_prev);
+            pending = -1;
+            h_prev = h;
+            if (!clipped) {
+                double g = (r == 0.0) ? o->grow_max : fmin(o->grow_max, o->safety * o->tol / r);
+                step = h * g;
+                if (t < t_end) {
+                    /* a proposal point: features of the accepted state, with the depletion
+                       rates the step used */
+                    orc_mlp_features(n_species, Y, kd, h, o->tol, x);
+                    int32_t q32 = INT32_MIN;
+                    if (learned) {
+                        if (q_replay && n_prop < n_replay) {
+                            q32 = q_replay[n_prop];
+                        } else {
+                            double ov = orc_mlp_forward(mlp, x);
+                            q32 = (int32_t)rint(32.0 * fmin(fmax(ov, -3.0), 3.0));
+                        }
+                        int qa = (int)floor(q32 / 32.0);
+                        int qb = q32 - 32 * qa;
+                        plain_step = step;
+                        step = ldexp(h * pow2[qb], qa);
+                        mlp_attempt = 1;
+                    }
+                    if (lg && n_prop < lg->capacity) {
+                        if (lg->q)
+                            lg->q[n_prop] = q32;
+                        if (lg->feat)
+                            memcpy(lg->feat + n_prop * ORC_MLP_IN, x, sizeof(x));
+                        if (lg->label)
+                            lg->label[n_prop] = NAN;
+                        if (lg->n_acc)
+                            lg->n_acc[n_prop] = n_acc;
+                        pending = n_prop;
+                    }
+                    n_prop++;
+                }
+            }
+        } else {
+            n_rej++;
+            if (mlp_attempt) {
+                mlp_attempt = 0;
+                step = plain_step;
+            } else {
+                double s = isinf(r) ? o->shrink_min : fmax(o->shrink_min, o->safety * o->tol / r);
+                step = h * s;
+            }
+            if (step < o->dt_min) {
+                status = ORC_ZONE_DT_UNDERFLOW;
+                break;
+            }
+        }
+    }
+    free(Fp);
+    free(kd);
+    free(Yn);
+    *dt = step;
+    *n_acc_out = n_acc;
+    *n_rej_out = n_rej;
+    if (lg)
+        lg->count = n_prop;
+    return status;
+}

@@ -33,7 +33,21 @@ EXPORTS = (
     "asy_autotune",
     "asy_last_error",
     "asy_version",
+    "asy_mlp_create",
+    "asy_mlp_destroy",
+    "asy_mlp_set_params",
+    "asy_mlp_get_params",
+    "asy_mlp_forward",
+    "asy_mlp_gradient",
+    "asy_mlp_train_step",
+    "asy_mlp_infer",
+    "asy_set_mlp",
+    "asy_integrate_batch_trace",
 )
+
+MLP_N_IN = 166
+MLP_N_PARAMS = 41345
+TRACE_REC = 170
 
 
 class AsyError(RuntimeError):
@@ -114,6 +128,22 @@ def lib():
         L.asy_last_error.restype = C.c_char_p
         L.asy_version.argtypes = []
         L.asy_version.restype = C.c_char_p
+        F = C.c_float
+        L.asy_mlp_create.argtypes = [I32, C.POINTER(P)]
+        L.asy_mlp_destroy.argtypes = [P]
+        L.asy_mlp_destroy.restype = None
+        L.asy_mlp_set_params.argtypes = [P, P]
+        L.asy_mlp_get_params.argtypes = [P, P]
+        L.asy_mlp_forward.argtypes = [P, I32, P, P, P]
+        L.asy_mlp_gradient.argtypes = [P, I32, P, P, P, P, P]
+        L.asy_mlp_train_step.argtypes = [P, I32, P, P, F, P, P]
+        L.asy_mlp_infer.argtypes = [P, I32, P, P, P]
+        L.asy_set_mlp.argtypes = [P, P]
+        L.asy_integrate_batch_trace.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, P,
+                                                P, P, P, C.c_int64, P, I32, I32, P]
+        for name in ("asy_mlp_create", "asy_mlp_set_params", "asy_mlp_get_params", "asy_mlp_forward",
+                     "asy_mlp_gradient", "asy_mlp_train_step", "asy_mlp_infer", "asy_set_mlp"):
+            getattr(L, name).restype = I32
         _ = I64
         _lib = L
     return _lib
@@ -211,6 +241,33 @@ def asy_integrate_batch(handle, n_species, n_reactions, Y, t_end, dt, n_accepted
     _check(st, "asy_integrate_batch")
 
 
+def asy_integrate_batch_trace(handle, n_species, n_reactions, Y, t_end, dt, n_accepted, n_rejected,
+                              zone_status, trace, count, stride, trace_zones, T=None, k_zone=None,
+                              opts: Optional[asy_options] = None, stream=None):
+    """asy_integrate_batch that also writes training records into trace [capacity, TRACE_REC]."""
+    import torch
+
+    Z = int(Y.shape[0])
+    cap = int(trace.shape[0])
+    args = [
+        _dev_ptr(Y, torch.float64, (Z, n_species), "Y"),
+        _dev_ptr(T, torch.float64, (Z,), "T"),
+        _dev_ptr(k_zone, torch.float64, (Z, n_reactions), "k_zone"),
+        _dev_ptr(t_end, torch.float64, (Z,), "t_end"),
+        _dev_ptr(dt, torch.float64, (Z,), "dt"),
+        _dev_ptr(n_accepted, torch.int64, (Z,), "n_accepted"),
+        _dev_ptr(n_rejected, torch.int64, (Z,), "n_rejected"),
+        _dev_ptr(zone_status, torch.int32, (Z,), "zone_status"),
+        _dev_ptr(trace, torch.float32, (cap, TRACE_REC), "trace"),
+        cap,
+        _dev_ptr(count, torch.int64, (1,), "count"),
+        int(stride), int(trace_zones),
+    ]
+    st = lib().asy_integrate_batch_trace(handle, None if opts is None else C.byref(opts), Z, *args,
+                                         _stream_ptr(stream))
+    _check(st, "asy_integrate_batch_trace")
+
+
 def asy_get_launch(handle) -> asy_launch:
     c = asy_launch()
     _check(lib().asy_get_launch(handle, C.byref(c)), "asy_get_launch")
@@ -288,8 +345,98 @@ class Network:
                             buf["dt"], buf["n_accepted"], buf["n_rejected"], buf["zone_status"],
                             T=buf["T"], k_zone=buf["k_zone"], opts=opts, stream=stream)
 
+    def integrate_trace(self, buf, trace, count, stride=1, trace_zones=None, opts=None,
+                        stream=None):
+        Z = int(buf["Y"].shape[0])
+        asy_integrate_batch_trace(self.handle, self.n_species, self.n_reactions, buf["Y"],
+                                  buf["t_end"], buf["dt"], buf["n_accepted"], buf["n_rejected"],
+                                  buf["zone_status"], trace, count, stride,
+                                  Z if trace_zones is None else trace_zones, T=buf["T"],
+                                  k_zone=buf["k_zone"], opts=opts, stream=stream)
+
+    def set_mlp(self, mlp: "Mlp"):
+        asy_set_mlp(self.handle, mlp)
+
     def set_launch(self, **fields):
         asy_set_launch(self.handle, **fields)
 
     def get_launch(self) -> dict:
         return asy_get_launch(self.handle).as_dict()
+
+
+class Mlp:
+    """Owner of an asy_mlp training context (device memory for batches of batch_max)."""
+
+    def __init__(self, batch_max: int):
+        h = C.c_void_p()
+        _check(lib().asy_mlp_create(int(batch_max), C.byref(h)), "asy_mlp_create")
+        self.handle = h.value
+        self.batch_max = int(batch_max)
+
+    def close(self):
+        if self.handle:
+            lib().asy_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_N_PARAMS,):
+            raise ValueError(f"params must have {MLP_N_PARAMS} values")
+        _check(lib().asy_mlp_set_params(self.handle, p.ctypes.data), "asy_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(MLP_N_PARAMS, dtype=np.float32)
+        _check(lib().asy_mlp_get_params(self.handle, p.ctypes.data), "asy_mlp_get_params")
+        return p
+
+    def _xy(self, x, y=None):
+        import torch
+
+        n = int(x.shape[0])
+        xp = _dev_ptr(x, torch.float32, (n, MLP_N_IN), "x")
+        yp = None if y is None else _dev_ptr(y, torch.float32, (n,), "y")
+        return n, xp, yp
+
+    def forward(self, x, stream=None):
+        import torch
+
+        n, xp, _ = self._xy(x)
+        o = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(lib().asy_mlp_forward(self.handle, n, xp, o.data_ptr(), _stream_ptr(stream)),
+               "asy_mlp_forward")
+        return o
+
+    def infer(self, x, stream=None):
+        import torch
+
+        n, xp, _ = self._xy(x)
+        o = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(lib().asy_mlp_infer(self.handle, n, xp, o.data_ptr(), _stream_ptr(stream)),
+               "asy_mlp_infer")
+        return o
+
+    def gradient(self, x, y, stream=None):
+        import torch
+
+        n, xp, yp = self._xy(x, y)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=x.device)
+        _check(lib().asy_mlp_gradient(self.handle, n, xp, yp, loss.data_ptr(), grad.data_ptr(),
+                                      _stream_ptr(stream)), "asy_mlp_gradient")
+        return loss, grad
+
+    def train_step(self, x, y, lr=1e-3, loss=None, stream=None):
+        n, xp, yp = self._xy(x, y)
+        _check(lib().asy_mlp_train_step(self.handle, n, xp, yp, float(lr),
+                                        None if loss is None else loss.data_ptr(),
+                                        _stream_ptr(stream)), "asy_mlp_train_step")
+
+
+def asy_set_mlp(net_handle, mlp: "Mlp"):
+    _check(lib().asy_set_mlp(net_handle, mlp.handle), "asy_set_mlp")

@@ -12,6 +12,7 @@
 
 #include "asynet.h"
 #include "integrate_kernels.h"
+#include "mlp_kernels.h"
 #include "stratified_kernel.h"
 
 using namespace asynet;
@@ -70,20 +71,46 @@ struct asy_network {
     asy_launch launch{};
     hipStream_t capture_stream = nullptr;
     GraphCache graph;
+    // learned controller: weights arranged for in-kernel inference (asy_set_mlp)
+    void *mlp_block = nullptr;
+    MlpDevice mlp{};
+    bool has_mlp = false;
+    const double *pow2 = nullptr;  // device [32]: 2^(b/32), in mlp_block
+};
+
+struct asy_mlp {
+    int32_t batch_max = 0;  // rounded up to a multiple of 32
+    int device = 0;
+    void *block = nullptr;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // [kMlpParams]
+    float *b3pad = nullptr;                                         // [16]
+    uint16_t *W1b = nullptr, *W2b = nullptr, *W3b = nullptr;
+    uint16_t *w1s = nullptr, *w2s = nullptr, *w3s = nullptr;
+    uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr, *g_ob = nullptr, *g_a2b = nullptr,
+             *g_a1b = nullptr;
+    float *a1 = nullptr, *a2 = nullptr, *out16 = nullptr, *o = nullptr, *g_o = nullptr,
+          *g_a2 = nullptr, *g_a1 = nullptr;
+    int64_t t = 0;  // Adam steps taken
 };
 
 namespace {
 
 // ---- variant 1 kernel instances -----------------------------------------------------------
 
-using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *, const int32_t *);
+using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *, const int32_t *,
+                             LearnArgs);
 
+// mode: 0 plain controller, 1 plain with trace, 2 learned, 3 learned with trace
 struct StratInstance {
-    int W, SPL, C;
+    int W, SPL, C, mode;
     StratKernel fn;
 };
 
-#define ASY_STRAT(W_, SPL_, C_) {W_, SPL_, C_, integrate_strat_kernel<W_, SPL_, C_>}
+#define ASY_STRAT(W_, SPL_, C_) {W_, SPL_, C_, 0, integrate_strat_kernel<W_, SPL_, C_, 2, false, false>}
+#define ASY_STRAT_LEARN(W_, SPL_, C_)                                                           \
+    {W_, SPL_, C_, 1, integrate_strat_kernel<W_, SPL_, C_, 2, false, true>},                    \
+    {W_, SPL_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                    \
+    {W_, SPL_, C_, 3, integrate_strat_kernel<W_, SPL_, C_, 2, true, true>}
 const StratInstance kStratInstances[] = {
     ASY_STRAT(1, 1, 16), ASY_STRAT(1, 1, 32), ASY_STRAT(1, 2, 32), ASY_STRAT(1, 2, 64),
     ASY_STRAT(1, 3, 64), ASY_STRAT(1, 3, 104), ASY_STRAT(1, 3, 112), ASY_STRAT(1, 4, 64),
@@ -91,14 +118,17 @@ const StratInstance kStratInstances[] = {
     ASY_STRAT(2, 2, 80), ASY_STRAT(2, 3, 64), ASY_STRAT(2, 3, 96), ASY_STRAT(2, 3, 136),
     ASY_STRAT(4, 1, 32), ASY_STRAT(4, 1, 48), ASY_STRAT(4, 1, 56), ASY_STRAT(4, 1, 64),
     ASY_STRAT(4, 2, 48), ASY_STRAT(4, 2, 64), ASY_STRAT(4, 2, 80), ASY_STRAT(4, 2, 96),
+    ASY_STRAT_LEARN(1, 1, 16), ASY_STRAT_LEARN(2, 2, 64), ASY_STRAT_LEARN(2, 2, 72),
 };
 #undef ASY_STRAT
+#undef ASY_STRAT_LEARN
 
-const StratInstance *find_strat_instance(int W, int SPL, int C_needed)
+const StratInstance *find_strat_instance(int W, int SPL, int C_needed, int mode = 0)
 {
     const StratInstance *best = nullptr;
     for (const auto &in : kStratInstances)
-        if (in.W == W && in.SPL == SPL && in.C >= C_needed && (!best || in.C < best->C))
+        if (in.W == W && in.SPL == SPL && in.mode == mode && in.C >= C_needed &&
+            (!best || in.C < best->C))
             best = &in;
     return best;
 }
@@ -282,7 +312,7 @@ hipError_t launch_variant0(asy_network *net, const DevOptions &o, const ZoneArgs
 // Queue every kernel of one call on stream s (no allocation, no host sync, so
 // the sequence can be captured into a graph).
 hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o,
-                      const ZoneArgs &za, hipStream_t s)
+                      const ZoneArgs &za, hipStream_t s, int mode = 0, LearnArgs la = LearnArgs{})
 {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, za.queue);
     hipError_t e = hipGetLastError();
@@ -319,13 +349,19 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
                 return e;
             order = net->order_buf;
         }
-        const StratInstance *inst = find_strat_instance(W, L.SPL, L.C);
+        const StratInstance *inst = find_strat_instance(W, L.SPL, L.C, mode);
+        if (!inst)
+            return hipErrorInvalidDeviceFunction;
+        if (mode >= 2) {
+            la.mlp = net->mlp;
+            la.pow2 = net->pow2;
+        }
         const int zpg = c.zones_per_group;
         int grid = (za.n_zones + zpg - 1) / zpg;
         if (c.groups_per_cu > 0)
             grid = std::min(grid, c.groups_per_cu * net->n_cu);
         hipLaunchKernelGGL(inst->fn, dim3(grid), dim3(c.threads_per_zone * zpg),
-                           lds_bytes_variant1(net, zpg), s, L.sn, o, za, rates, order);
+                           lds_bytes_variant1(net, zpg), s, L.sn, o, za, rates, order, la);
         return hipGetLastError();
     }
     int grid = za.n_zones;
@@ -365,8 +401,6 @@ asy_status validate_options(const asy_options *o)
         return fail(ASY_EINVAL, "max_steps must be >= 0");
     if (o->controller != ASY_CTRL_PLAIN && o->controller != ASY_CTRL_LEARNED)
         return fail(ASY_EINVAL, "unknown controller");
-    if (o->controller == ASY_CTRL_LEARNED)
-        return fail(ASY_ENOTSUP, "learned controller not available in this build");
     if (o->reserved != 0)
         return fail(ASY_EINVAL, "asy_options.reserved must be 0");
     return ASY_OK;
@@ -423,16 +457,19 @@ void append_bytes(std::vector<uint8_t> &key, const T &v)
 // Queue one call, replaying a captured graph when the launch is identical to
 // the previous one (same configuration, options, sizes and buffers).
 asy_status enqueue(asy_network *net, const asy_launch &c, const DevOptions &o, const ZoneArgs &za,
-                   hipStream_t s)
+                   hipStream_t s, int mode = 0, const LearnArgs &la = LearnArgs{})
 {
     if (!c.use_graph) {
-        HIP_TRY(launch_all(net, c, o, za, s));
+        HIP_TRY(launch_all(net, c, o, za, s, mode, la));
         return ASY_OK;
     }
     std::vector<uint8_t> key;
     append_bytes(key, c);
     append_bytes(key, o);
     append_bytes(key, za);
+    append_bytes(key, mode);
+    append_bytes(key, la);
+    append_bytes(key, net->mlp);
     if (net->graph.exec == nullptr || key != net->graph.key) {
         if (net->graph.exec) {
             HIP_TRY(hipGraphExecDestroy(net->graph.exec));
@@ -442,7 +479,7 @@ asy_status enqueue(asy_network *net, const asy_launch &c, const DevOptions &o, c
         if (!net->capture_stream)
             HIP_TRY(hipStreamCreateWithFlags(&net->capture_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(net->capture_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = launch_all(net, c, o, za, net->capture_stream);
+        hipError_t le = launch_all(net, c, o, za, net->capture_stream, mode, la);
         hipGraph_t graph = nullptr;
         hipError_t ee = hipStreamEndCapture(net->capture_stream, &graph);
         if (le != hipSuccess || ee != hipSuccess) {
@@ -467,6 +504,88 @@ DevOptions to_dev(const asy_options &o)
 {
     return DevOptions{o.kappa, o.tol, o.y_floor, o.grow_max, o.safety, o.shrink_min, o.dt_min,
                       o.max_steps};
+}
+
+// ---- learned step proposer: host side --------------------------------------------------------
+
+template <bool TA, bool TB>
+hipError_t launch_gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
+                       float *C32, uint16_t *Cb, int ldc, const float *bias, const float *pre,
+                       int epi, int n_store, hipStream_t s)
+{
+    const int tiles = (M / 16) * (N / 16);
+    hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB>), dim3((tiles + 3) / 4), dim3(256), 0, s, M, N, K,
+                       A, lda, B, ldb, C32, Cb, ldc, bias, pre, epi, n_store);
+    return hipGetLastError();
+}
+
+int mlp_pad(int n) { return (n + 31) / 32 * 32; }
+
+// Forward pass on n samples (rows padded to a multiple of 32 with zeros).
+hipError_t mlp_forward_pass(asy_mlp *m, int n, const float *x, hipStream_t s)
+{
+    const int B = mlp_pad(n);
+    hipLaunchKernelGGL(mlp_cast_weights_kernel, dim3(64), dim3(256), 0, s, m->p, m->W1b, m->W2b,
+                       m->W3b);
+    hipLaunchKernelGGL(mlp_pack_input_kernel, dim3(64), dim3(256), 0, s, n, B, x, m->xb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    e = launch_gemm<false, false>(B, kMlpHid, kMlpInPad, m->xb, kMlpInPad, m->W1b, kMlpHid, m->a1,
+                                  m->h1b, kMlpHid, m->p + kOffB1, nullptr, kEpiForward, kMlpHid, s);
+    if (e != hipSuccess)
+        return e;
+    e = launch_gemm<false, false>(B, kMlpHid, kMlpHid, m->h1b, kMlpHid, m->W2b, kMlpHid, m->a2,
+                                  m->h2b, kMlpHid, m->p + kOffB2, nullptr, kEpiForward, kMlpHid, s);
+    if (e != hipSuccess)
+        return e;
+    return launch_gemm<false, false>(B, 16, kMlpHid, m->h2b, kMlpHid, m->W3b, 16, m->out16, nullptr,
+                                     16, m->b3pad, nullptr, kEpiStore, 16, s);
+}
+
+// Forward, loss and gradient into m->g.
+hipError_t mlp_gradient_pass(asy_mlp *m, int n, const float *x, const float *y, float *loss,
+                             hipStream_t s)
+{
+    const int B = mlp_pad(n);
+    hipError_t e = mlp_forward_pass(m, n, x, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(mlp_loss_kernel, dim3(1), dim3(1024), 0, s, n, B, m->out16, y, m->o, m->g_o,
+                       m->g_ob, loss);
+    hipLaunchKernelGGL(mlp_out_grad_kernel, dim3(64), dim3(256), 0, s, B, m->g_ob, m->W3b, m->a2,
+                       m->g_a2, m->g_a2b);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    // g_a1 = (g_a2b W2b^T) [a1 > 0]
+    e = launch_gemm<false, true>(B, kMlpHid, kMlpHid, m->g_a2b, kMlpHid, m->W2b, kMlpHid, m->g_a1,
+                                 m->g_a1b, kMlpHid, nullptr, m->a1, kEpiReluGrad, kMlpHid, s);
+    if (e != hipSuccess)
+        return e;
+    // dW2 = h1b^T g_a2b, dW1 = xb^T g_a1b
+    e = launch_gemm<true, false>(kMlpHid, kMlpHid, B, m->h1b, kMlpHid, m->g_a2b, kMlpHid,
+                                 m->g + kOffW2, nullptr, kMlpHid, nullptr, nullptr, kEpiStore, kMlpHid, s);
+    if (e != hipSuccess)
+        return e;
+    e = launch_gemm<true, false>(kMlpInPad, kMlpHid, B, m->xb, kMlpInPad, m->g_a1b, kMlpHid,
+                                 m->g + kOffW1, nullptr, kMlpHid, nullptr, nullptr, kEpiStore, kMlpHid, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(192), 0, s, B, m->g_a1, m->g_a2, m->g_o,
+                       m->h2b, m->g_ob, m->g);
+    return hipGetLastError();
+}
+
+asy_status mlp_check(const asy_mlp *m, int32_t n, const void *x)
+{
+    if (!m)
+        return fail(ASY_EINVAL, "mlp must be non-NULL");
+    if (n < 1 || n > m->batch_max)
+        return fail(ASY_EINVAL, "n must be in [1, batch_max]");
+    if (!x)
+        return fail(ASY_EINVAL, "x must be non-NULL");
+    return ASY_OK;
 }
 
 }  // namespace
@@ -697,6 +816,8 @@ void asy_network_destroy(asy_network *net)
     for (auto &L : net->strat)
         if (L.dev)
             (void)hipFree(L.dev);
+    if (net->mlp_block)
+        (void)hipFree(net->mlp_block);
     if (net->rate_buf)
         (void)hipFree(net->rate_buf);
     if (net->key_buf)
@@ -725,10 +846,13 @@ asy_status asy_set_launch(asy_network *net, const asy_launch *cfg)
     return ASY_OK;
 }
 
-asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_t n_zones,
-                               double *Y, const double *T, const double *k_zone,
-                               const double *t_end, double *dt, int64_t *n_accepted,
-                               int64_t *n_rejected, int32_t *zone_status, void *stream)
+namespace {
+
+// Shared argument checks and launch of asy_integrate_batch and asy_integrate_batch_trace.
+asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n_zones, double *Y,
+                            const double *T, const double *k_zone, const double *t_end, double *dt,
+                            int64_t *n_accepted, int64_t *n_rejected, int32_t *zone_status,
+                            void *stream, bool trace, LearnArgs la)
 {
     g_last_error.clear();
     if (!net)
@@ -742,6 +866,24 @@ asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_
         return st;
     if (n_zones < 0)
         return fail(ASY_EINVAL, "n_zones must be >= 0");
+    if (trace && (!la.trace || !la.count || la.capacity < 0 || la.capacity > INT32_MAX ||
+                  la.stride < 1 || la.trace_zones < 0))
+        return fail(ASY_EINVAL, "trace needs buffers, 0 <= capacity < 2^31, stride >= 1, "
+                                "trace_zones >= 0");
+    const bool learned = o.controller == ASY_CTRL_LEARNED;
+    const int mode = (learned ? 2 : 0) + (trace ? 1 : 0);
+    if (mode != 0) {
+        if (net->n_species > ASY_MLP_N_IN - 4)
+            return fail(ASY_ENOTSUP, "learned controller and trace take at most 162 species");
+        if (learned && !net->has_mlp)
+            return fail(ASY_ESTATE, "the learned controller needs asy_set_mlp first");
+        if (net->launch.variant != 1)
+            return fail(ASY_ENOTSUP, "learned controller and trace need launch variant 1");
+        const StratLayout &L = net->strat[w_index(net->launch.threads_per_zone / 64)];
+        if (!find_strat_instance(L.W, L.SPL, L.C, mode))
+            return fail(ASY_ENOTSUP, "no learned/trace kernel instance for this network and "
+                                     "launch configuration");
+    }
     if (n_zones == 0)
         return ASY_OK;
     if (!Y || !t_end || !dt || !n_accepted || !n_rejected || !zone_status)
@@ -758,7 +900,35 @@ asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_
     st = ensure_call_bufs(net, net->launch, n_zones, s);
     if (st != ASY_OK)
         return st;
-    return enqueue(net, net->launch, to_dev(o), za, s);
+    return enqueue(net, net->launch, to_dev(o), za, s, mode, la);
+}
+
+}  // namespace
+
+asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_t n_zones,
+                               double *Y, const double *T, const double *k_zone,
+                               const double *t_end, double *dt, int64_t *n_accepted,
+                               int64_t *n_rejected, int32_t *zone_status, void *stream)
+{
+    return integrate_common(net, opts, n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected,
+                            zone_status, stream, false, LearnArgs{});
+}
+
+asy_status asy_integrate_batch_trace(asy_network *net, const asy_options *opts, int32_t n_zones,
+                                     double *Y, const double *T, const double *k_zone,
+                                     const double *t_end, double *dt, int64_t *n_accepted,
+                                     int64_t *n_rejected, int32_t *zone_status, float *trace,
+                                     int64_t capacity, unsigned long long *count, int32_t stride,
+                                     int32_t trace_zones, void *stream)
+{
+    LearnArgs la{};
+    la.trace = trace;
+    la.capacity = capacity;
+    la.count = count;
+    la.stride = stride;
+    la.trace_zones = trace_zones;
+    return integrate_common(net, opts, n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected,
+                            zone_status, stream, true, la);
 }
 
 asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sample_zones,
@@ -854,6 +1024,199 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
     if (best)
         *best = net->launch;
     return result;
+}
+
+asy_status asy_mlp_create(int32_t batch_max, asy_mlp **out)
+{
+    g_last_error.clear();
+    if (!out || batch_max < 1 || batch_max > (1 << 20))
+        return fail(ASY_EINVAL, "batch_max must be in [1, 2^20] and out non-NULL");
+    auto *m = new asy_mlp();
+    m->batch_max = batch_max;
+    const size_t B = (size_t)mlp_pad(batch_max);
+    HIP_TRY(hipGetDevice(&m->device));
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t P = kMlpParams;
+    const size_t o_p = carve(P * 4), o_g = carve(P * 4), o_m = carve(P * 4), o_v = carve(P * 4);
+    const size_t o_b3 = carve(16 * 4);
+    const size_t o_W1 = carve(kMlpInPad * kMlpHid * 2), o_W2 = carve(kMlpHid * kMlpHid * 2);
+    const size_t o_W3 = carve(kMlpHid * 16 * 2);
+    const size_t o_s1 = carve(8 * 6 * 64 * 8 * 2), o_s2 = carve(8 * 4 * 64 * 8 * 2);
+    const size_t o_s3 = carve(4 * 64 * 8 * 2);
+    const size_t o_xb = carve(B * kMlpInPad * 2), o_h1 = carve(B * kMlpHid * 2);
+    const size_t o_h2 = carve(B * kMlpHid * 2), o_gob = carve(B * 2), o_ga2b = carve(B * kMlpHid * 2);
+    const size_t o_ga1b = carve(B * kMlpHid * 2);
+    const size_t o_a1 = carve(B * kMlpHid * 4), o_a2 = carve(B * kMlpHid * 4), o_o16 = carve(B * 16 * 4);
+    const size_t o_o = carve(B * 4), o_go = carve(B * 4), o_ga2 = carve(B * kMlpHid * 4);
+    const size_t o_ga1 = carve(B * kMlpHid * 4);
+    hipError_t e = hipMalloc(&m->block, off);
+    if (e != hipSuccess) {
+        delete m;
+        return fail(ASY_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    char *b = static_cast<char *>(m->block);
+    e = hipMemset(b, 0, off);
+    if (e != hipSuccess) {
+        asy_mlp_destroy(m);
+        return fail(ASY_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
+    }
+    auto F = [&](size_t o) { return reinterpret_cast<float *>(b + o); };
+    auto H = [&](size_t o) { return reinterpret_cast<uint16_t *>(b + o); };
+    m->p = F(o_p); m->g = F(o_g); m->m = F(o_m); m->v = F(o_v); m->b3pad = F(o_b3);
+    m->W1b = H(o_W1); m->W2b = H(o_W2); m->W3b = H(o_W3);
+    m->w1s = H(o_s1); m->w2s = H(o_s2); m->w3s = H(o_s3);
+    m->xb = H(o_xb); m->h1b = H(o_h1); m->h2b = H(o_h2); m->g_ob = H(o_gob); m->g_a2b = H(o_ga2b);
+    m->g_a1b = H(o_ga1b);
+    m->a1 = F(o_a1); m->a2 = F(o_a2); m->out16 = F(o_o16); m->o = F(o_o); m->g_o = F(o_go);
+    m->g_a2 = F(o_ga2); m->g_a1 = F(o_ga1);
+    *out = m;
+    return ASY_OK;
+}
+
+void asy_mlp_destroy(asy_mlp *m)
+{
+    if (!m)
+        return;
+    (void)hipDeviceSynchronize();
+    if (m->block)
+        (void)hipFree(m->block);
+    delete m;
+}
+
+asy_status asy_mlp_set_params(asy_mlp *m, const float *params)
+{
+    g_last_error.clear();
+    if (!m || !params)
+        return fail(ASY_EINVAL, "mlp and params must be non-NULL");
+    HIP_TRY(hipMemcpy(m->p, params, kMlpParams * 4, hipMemcpyHostToDevice));
+    float b3pad[16] = {params[kOffB3]};
+    HIP_TRY(hipMemcpy(m->b3pad, b3pad, sizeof(b3pad), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(m->m, 0, kMlpParams * 4));
+    HIP_TRY(hipMemset(m->v, 0, kMlpParams * 4));
+    m->t = 0;
+    return ASY_OK;
+}
+
+asy_status asy_mlp_get_params(const asy_mlp *m, float *params)
+{
+    g_last_error.clear();
+    if (!m || !params)
+        return fail(ASY_EINVAL, "mlp and params must be non-NULL");
+    HIP_TRY(hipMemcpy(params, m->p, kMlpParams * 4, hipMemcpyDeviceToHost));
+    return ASY_OK;
+}
+
+asy_status asy_mlp_forward(asy_mlp *m, int32_t n, const float *x, float *o, void *stream)
+{
+    g_last_error.clear();
+    asy_status st = mlp_check(m, n, x);
+    if (st != ASY_OK)
+        return st;
+    if (!o)
+        return fail(ASY_EINVAL, "o must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(mlp_forward_pass(m, n, x, s));
+    hipLaunchKernelGGL(mlp_loss_kernel, dim3(1), dim3(1024), 0, s, n, n, m->out16, nullptr, o,
+                       nullptr, nullptr, nullptr);
+    HIP_TRY(hipGetLastError());
+    return ASY_OK;
+}
+
+asy_status asy_mlp_gradient(asy_mlp *m, int32_t n, const float *x, const float *y, float *loss,
+                            float *grad, void *stream)
+{
+    g_last_error.clear();
+    asy_status st = mlp_check(m, n, x);
+    if (st != ASY_OK)
+        return st;
+    if (!y || !grad)
+        return fail(ASY_EINVAL, "y and grad must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(mlp_gradient_pass(m, n, x, y, loss, s));
+    HIP_TRY(hipMemcpyAsync(grad, m->g, kMlpParams * 4, hipMemcpyDeviceToDevice, s));
+    return ASY_OK;
+}
+
+asy_status asy_mlp_train_step(asy_mlp *m, int32_t n, const float *x, const float *y, float lr,
+                              float *loss, void *stream)
+{
+    g_last_error.clear();
+    asy_status st = mlp_check(m, n, x);
+    if (st != ASY_OK)
+        return st;
+    if (!y || !(lr > 0.0f) || !std::isfinite(lr))
+        return fail(ASY_EINVAL, "y must be non-NULL and lr finite and > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(mlp_gradient_pass(m, n, x, y, loss, s));
+    m->t += 1;
+    const double beta1 = 0.9, beta2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(beta1, (double)m->t));
+    const float c2 = (float)(1.0 - std::pow(beta2, (double)m->t));
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->m, m->v, lr,
+                       (float)beta1, (float)beta2, 1e-8f, c1, c2);
+    HIP_TRY(hipGetLastError());
+    return ASY_OK;
+}
+
+asy_status asy_mlp_infer(asy_mlp *m, int32_t n, const float *x, float *o, void *stream)
+{
+    g_last_error.clear();
+    asy_status st = mlp_check(m, n, x);
+    if (st != ASY_OK)
+        return st;
+    if (!o)
+        return fail(ASY_EINVAL, "o must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float b3 = 0.0f;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(&b3, m->p + kOffB3, 4, hipMemcpyDeviceToHost));
+    hipLaunchKernelGGL(mlp_swizzle_kernel, dim3(64), dim3(256), 0, s, m->p, m->w1s, m->w2s, m->w3s);
+    HIP_TRY(hipGetLastError());
+    MlpDevice w{m->w1s, m->w2s, m->w3s, m->p + kOffB1, m->p + kOffB2, b3};
+    hipLaunchKernelGGL(mlp_infer_batch_kernel, dim3(std::min(n, 4096)), dim3(64), 0, s, n, x, w, o);
+    HIP_TRY(hipGetLastError());
+    return ASY_OK;
+}
+
+asy_status asy_set_mlp(asy_network *net, const asy_mlp *m)
+{
+    g_last_error.clear();
+    if (!net || !m)
+        return fail(ASY_EINVAL, "net and mlp must be non-NULL");
+    if (net->n_species > ASY_MLP_N_IN - 4)
+        return fail(ASY_ENOTSUP, "the learned controller takes at most 162 species");
+    HIP_TRY(hipSetDevice(net->device));
+    if (!net->mlp_block) {
+        const size_t bytes = (8 * 6 + 8 * 4 + 4) * 64 * 8 * 2 + 2 * kMlpHid * 4 + 32 * 8;
+        HIP_TRY(hipMalloc(&net->mlp_block, bytes));
+    }
+    uint16_t *w = static_cast<uint16_t *>(net->mlp_block);
+    uint16_t *w1s = w, *w2s = w1s + 8 * 6 * 64 * 8, *w3s = w2s + 8 * 4 * 64 * 8;
+    float *bias = reinterpret_cast<float *>(w3s + 4 * 64 * 8);
+    double *pow2 = reinterpret_cast<double *>(bias + 2 * kMlpHid);
+    {
+        double tab[32];
+        for (int b = 0; b < 32; ++b)
+            tab[b] = std::exp2(b / 32.0);
+        HIP_TRY(hipMemcpy(pow2, tab, sizeof(tab), hipMemcpyHostToDevice));
+        net->pow2 = pow2;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    hipLaunchKernelGGL(mlp_swizzle_kernel, dim3(64), dim3(256), 0, nullptr, m->p, w1s, w2s, w3s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpy(bias, m->p + kOffB1, kMlpHid * 4, hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemcpy(bias + kMlpHid, m->p + kOffB2, kMlpHid * 4, hipMemcpyDeviceToDevice));
+    float b3 = 0.0f;
+    HIP_TRY(hipMemcpy(&b3, m->p + kOffB3, 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipDeviceSynchronize());
+    net->mlp = MlpDevice{w1s, w2s, w3s, bias, bias + kMlpHid, b3};
+    net->has_mlp = true;
+    return ASY_OK;
 }
 
 }  // extern "C"

@@ -101,6 +101,28 @@ __device__ inline double wave_max_dpp(double v)
     return __hiloint2double(hi, lo);
 }
 
+#define ASY_DPP_SUM_STEP(v, ctrl, rmask)                                                       \
+    do {                                                                                       \
+        const int lo_ = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, rmask, 0xf, false); \
+        const int hi_ = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, rmask, 0xf, false); \
+        v = v + __hiloint2double(hi_, lo_);                                                    \
+    } while (0)
+
+// Sum over the 64 lanes of a wave through DPP lane moves (lanes without a
+// source add +0.0).  The order of the additions is fixed.
+__device__ inline double wave_sum_dpp(double v)
+{
+    ASY_DPP_SUM_STEP(v, 0x111, 0xf);
+    ASY_DPP_SUM_STEP(v, 0x112, 0xf);
+    ASY_DPP_SUM_STEP(v, 0x114, 0xf);
+    ASY_DPP_SUM_STEP(v, 0x118, 0xf);
+    ASY_DPP_SUM_STEP(v, 0x142, 0xa);
+    ASY_DPP_SUM_STEP(v, 0x143, 0xc);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ inline int wave_or(int v)
 {
 #pragma unroll

@@ -22,6 +22,7 @@
 #pragma once
 
 #include "integrate_kernels.h"
+#include "mlp_kernels.h"
 
 namespace asynet {
 
@@ -129,6 +130,24 @@ zone_order_kernel(int32_t n_zones, const float *key, int32_t *order)
         order[base + i] = (int32_t)(v[i] & 0xffffffffu);
 }
 
+// Learned controller and trace output of variant 1.
+//  Trace record (kTraceRec floats) per sampled state n (after the n-th accepted step):
+//   [0, 166) features of the state, [166] label log2(h_{n+1} / h_n) of the step accepted
+//   next (NaN if the zone ended first or that step was clipped to t_end), [167] 32 q of
+//   the learned proposal made from the state (NaN for the plain controller), [168] zone,
+//   [169] n.
+constexpr int kTraceRec = 170;
+
+struct LearnArgs {
+    MlpDevice mlp;
+    const double *pow2;  // [32]: 2^(b/32)
+    float *trace;        // [capacity][kTraceRec] or nullptr
+    int64_t capacity;
+    unsigned long long *count;  // records taken (may exceed capacity)
+    int32_t stride;      // record every stride-th accepted state
+    int32_t trace_zones; // only zones below this index record
+};
+
 // LDS doubles one zone needs: Y[0..N] (Y[N] = 1.0) and out[0..2N] (out[2N] collects padding rows).
 __host__ __device__ inline int strat_zone_cells(int n_species)
 {
@@ -160,12 +179,17 @@ constexpr int strat_waves_per_eu()
     return 512 / (2 * C + 128) < 1 ? 1 : (512 / (2 * C + 128) > 8 ? 8 : 512 / (2 * C + 128));
 }
 
-template <int W, int SPL, int C, int GA = 2>
+template <int W, int SPL, int C, int GA = 2, bool LEARNED = false, bool TRACE = false>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
                                amdgpu_waves_per_eu(strat_waves_per_eu<C>())))
 integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates,
-                       const int32_t *order)
+                       const int32_t *order, LearnArgs la)
 {
+    constexpr bool FEATURES = LEARNED || TRACE;
+    __shared__ float feat[FEATURES ? kMlpInPad : 1];
+    __shared__ float hs[FEATURES ? kMlpHid : 1];
+    __shared__ double xw_sum[W];
+    __shared__ float xw_o;
     static_assert(C % 4 == 0, "slots come in blocks of 4");
     constexpr int LANES = 64 * W;
     extern __shared__ double lds[];
@@ -272,6 +296,14 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         double t = 0.0, step = dt0;
         int64_t nacc = 0, nrej = 0;
         int32_t status = kZoneOk;
+        double plain_step = dt0;   // learned: the plain proposal to fall back to
+        bool mlp_attempt = false;  // learned: the current attempt uses the network's proposal
+        double h_last = 0.0;       // last accepted step
+        int64_t rec_pending = -1;  // trace: record waiting for its label
+        if constexpr (FEATURES) {
+            for (int c = zl; c < kMlpInPad; c += 64 * W)
+                feat[c] = 0.0f;
+        }
         const uint64_t emask = sn.end_mask;
         constexpr int NB = C / 4;
         // the lane's row of every stratum (at most 2*SPL strata), kept in registers
@@ -411,10 +443,116 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                     const double g = (r == 0.0) ? o.grow_max : fmin(o.grow_max, o.safety * o.tol / r);
                     step = h * g;
                 }
+                mlp_attempt = false;
+                if constexpr (FEATURES) {
+                    // label of the state recorded before this step
+                    if (TRACE && rec_pending >= 0 && zl == 0)
+                        la.trace[rec_pending * kTraceRec + 166] =
+                            clipped ? NAN : (float)log2(h / h_last);
+                    rec_pending = -1;
+                    const bool propose = !clipped && t < t_end;
+                    const bool record = TRACE && propose && z < la.trace_zones &&
+                                        (nacc % la.stride) == 0;
+                    if ((LEARNED && propose) || record) {
+                        // features of the accepted state (depletion rates of this step)
+                        double kmax = 0.0, ksum = 0.0;
+#pragma unroll
+                        for (int m = 0; m < SPL; ++m) {
+                            const int i = zl + m * LANES;
+                            if (i < N) {
+                                const double y = yn[m];
+                                feat[i] = (float)(fmax(log10(fmax(y, 1e-300)), -30.0) / 30.0);
+                                const double kh = out[N + i] * h;
+                                kmax = fmax(kmax, kh);
+                                ksum += kh;
+                            }
+                        }
+                        kmax = wave_max_dpp(kmax);
+                        ksum = wave_sum_dpp(ksum);
+                        if constexpr (W > 1) {
+                            zone_sync<W>();
+                            if (lane == 0) {
+                                xw_r[wave] = kmax;
+                                xw_sum[wave] = ksum;
+                            }
+                            __syncthreads();
+                            kmax = xw_r[0];
+                            ksum = xw_sum[0];
+#pragma unroll
+                            for (int w = 1; w < W; ++w) {
+                                kmax = fmax(kmax, xw_r[w]);
+                                ksum += xw_sum[w];
+                            }
+                        }
+                        if (zl == 0) {
+                            feat[N] = (float)(log10(fmax(kmax, 1e-300)) / 10.0);
+                            feat[N + 1] = (float)(log10(fmax(ksum / N, 1e-300)) / 10.0);
+                            feat[N + 2] = (float)(log10(h) / 10.0);
+                            feat[N + 3] = (float)(log10(o.tol) / 10.0);
+                        }
+                        zone_sync<W>();
+                        int q32 = 0;
+                        if constexpr (LEARNED) {
+                            if (propose) {
+                                float ov = 0.0f;
+                                if (wave == 0)
+                                    ov = mlp_infer_wave(la.mlp, feat, hs, lane);
+                                if constexpr (W > 1) {
+                                    if (tid == 0)
+                                        xw_o = ov;
+                                    __syncthreads();
+                                    ov = xw_o;
+                                }
+                                const double oc = fmin(fmax((double)ov, -3.0), 3.0);
+                                q32 = (int)rint(32.0 * oc);
+                                const int qa = (q32 >= 0) ? q32 / 32 : -((31 - q32) / 32);
+                                const int qb = q32 - 32 * qa;
+                                plain_step = step;
+                                step = ldexp(h * la.pow2[qb], qa);
+                                mlp_attempt = true;
+                            }
+                        }
+                        if (record) {
+                            // slot of the record; -1 once the buffer is full (capacity < 2^31)
+                            int slot = -1;
+                            if (zl == 0) {
+                                const unsigned long long c = atomicAdd(la.count, 1ull);
+                                slot = (c < (unsigned long long)la.capacity) ? (int)c : -1;
+                            }
+                            slot = __shfl(slot, 0, kWave);
+                            if constexpr (W > 1) {
+                                if (tid == 0)
+                                    xw_zone = slot;
+                                __syncthreads();
+                                slot = xw_zone;
+                            }
+                            rec_pending = slot;
+                            if (slot >= 0) {
+                                float *rec = la.trace + rec_pending * kTraceRec;
+                                for (int c = zl; c < kMlpIn; c += 64 * W)
+                                    rec[c] = feat[c];
+                                if (zl == 0) {
+                                    rec[166] = NAN;
+                                    rec[167] = LEARNED ? (float)q32 : NAN;
+                                    rec[168] = (float)z;
+                                    rec[169] = (float)nacc;
+                                }
+                            }
+                        }
+                        zone_sync<W>();
+                    }
+                    h_last = h;
+                }
             } else {
                 ++nrej;
-                const double s = isinf(r) ? o.shrink_min : fmax(o.shrink_min, o.safety * o.tol / r);
-                step = h * s;
+                if (mlp_attempt) {
+                    // the network's proposal failed: continue with the plain rule
+                    mlp_attempt = false;
+                    step = plain_step;
+                } else {
+                    const double s = isinf(r) ? o.shrink_min : fmax(o.shrink_min, o.safety * o.tol / r);
+                    step = h * s;
+                }
                 if (step < o.dt_min) {
                     status = kZoneDtUnderflow;
                     break;

@@ -80,3 +80,116 @@ def test_adam_matches_torch():
 def test_quantize():
     q = mlp.quantize_log2_ratio([0.0, 1.0 / 64, 3.0 / 64, -5.0, 5.0, 0.49])
     assert list(q) == [0, 0, 2, -96, 96, 16]
+
+
+def test_c_reference_network_matches_numpy():
+    """The C network (used by the learned integration reference) equals the numpy one."""
+    import oracle
+
+    p = mlp.init_params(21).astype(np.float32)
+    u = mlp.unpack(p.astype(np.float64))
+    rng = np.random.default_rng(22)
+    u["b1"] = rng.normal(scale=0.1, size=128)
+    u["b2"] = rng.normal(scale=0.1, size=128)
+    u["W3"] = rng.normal(scale=0.3, size=128)
+    u["b3"] = np.array([-0.05])
+    p = mlp.pack(u).astype(np.float32)
+    x = rng.uniform(-1, 1, size=(20, mlp.N_IN)).astype(np.float32)
+    o_np, _ = mlp.forward(p.astype(np.float64), x.astype(np.float64))
+    o_c = np.array([oracle.mlp_forward_c(p, xi) for xi in x])
+    np.testing.assert_allclose(o_c, o_np, rtol=1e-12, atol=1e-12)
+
+
+def test_learned_reference_with_neutral_proposals_repeats_the_step():
+    """Replaying q = 0 proposes h_next = h: on A -> B every accepted step keeps the first step."""
+    import oracle
+    from tests.test_oracle_pins import DECAY
+
+    p = np.zeros(mlp.N_PARAMS, dtype=np.float32)
+    out = oracle.integrate_zone_learned(DECAY, np.array([1.0]), np.array([1.0, 1.0]), 0.05, 1e-3, p,
+                                        q_replay=np.zeros(100, np.int32), log_capacity=100)
+    assert out["status"] == oracle.ZONE_OK and out["n_rej"] == 0
+    assert out["n_acc"] == 50 and out["n_prop"] == 49 and (out["log"]["q"] == 0).all()
+    lg = out["log"]
+    np.testing.assert_array_equal(lg["n_acc"], np.arange(1, 50))
+    # every next step repeats h (label 0) except the last, clipped to t_end (NaN)
+    assert np.all(np.abs(lg["label"][:-1]) < 1e-9) and np.isnan(lg["label"][-1])
+    want = (1 - 1e-3) ** 50
+    assert out["Y"][0] == pytest.approx(want, rel=1e-12)
+    # with h = 0.009 the plain rule keeps h (r = h k), and every 2^3 proposal has r = 0.072 > tol:
+    # each is rejected and replaced by the plain proposal, except the last one, clipped to the
+    # 0.005 left before t_end exactly as the plain step is; the trajectory is the plain one
+    out = oracle.integrate_zone_learned(DECAY, np.array([1.0]), np.array([1.0, 1.0]), 0.5, 0.009, p,
+                                        q_replay=np.full(100, 96, np.int32))
+    plain = oracle.integrate_zone(DECAY, np.array([1.0]), np.array([1.0, 1.0]), 0.5, 0.009)
+    assert out["n_acc"] == plain["n_acc"] == 56 and plain["n_rej"] == 0
+    assert out["n_prop"] == 55 and out["n_rej"] == 54
+    np.testing.assert_array_equal(out["Y"], plain["Y"])
+
+
+def test_plain_log_follows_the_plain_trajectory():
+    """learned=False reproduces the plain integrator and logs the state features it passes."""
+    import oracle
+    from paper_1409_5826_amd import workloads as wl
+
+    w = wl.preset("n16_r48_const", n_zones=3)
+    for z in range(3):
+        plain = oracle.integrate_zone(w.network, w.zones.k[z], w.zones.Y0[z], w.zones.t_end[z],
+                                      w.zones.dt0[z], trace_capacity=100000)
+        out = oracle.integrate_zone_learned(w.network, w.zones.k[z], w.zones.Y0[z],
+                                            w.zones.t_end[z], w.zones.dt0[z], learned=False,
+                                            log_capacity=100000)
+        np.testing.assert_array_equal(out["Y"], plain["Y"])
+        assert (out["n_acc"], out["n_rej"], out["dt"]) == (plain["n_acc"], plain["n_rej"], plain["dt"])
+        lg = out["log"]
+        tr = plain["trace"]
+        hacc = tr["h"][tr["accepted"]]
+        # labels are log2 ratios of consecutive accepted steps
+        n = lg["n_acc"]
+        ok = ~np.isnan(lg["label"])
+        np.testing.assert_allclose(lg["label"][ok], np.log2(hacc[n[ok]] / hacc[n[ok] - 1]), rtol=0,
+                                   atol=1e-12)
+        # the step-size feature is log10 of the accepted step / 10, the tol feature is fixed
+        N = w.network.n_species
+        np.testing.assert_allclose(lg["feat"][:, N + 2], np.log10(hacc[n - 1]) / 10, rtol=1e-6)
+        assert np.all(lg["feat"][:, N + 3] == np.float32(np.log10(0.01) / 10))
+        assert np.all(lg["feat"][:, N + 4:] == 0) and np.all(lg["feat"][:, :N] <= 0)
+
+
+def test_features_of_a_decay_state():
+    """Features of a two-species state: Y = (0.5, 1e-40), depletion rates (3, 0), h = 0.01.
+
+    max k h = 0.03, mean k h = 0.015, log10 Y = (-0.30103, -40 -> floored at -30).
+    """
+    import oracle
+
+    x = oracle.mlp_features([0.5, 1e-40], [3.0, 0.0], 0.01, 1e-3)
+    assert x.dtype == np.float32 and x.shape == (166,)
+    want = [-0.30102999566398120 / 30, -1.0, -1.5228787452803376 / 10, -1.8239087409443189 / 10,
+            -0.2, -0.3]
+    np.testing.assert_allclose(x[:6], want, rtol=1e-6)
+    assert (x[6:] == 0).all()
+
+
+@pytest.mark.parametrize("b3,q", [(1.0 + 0.6 / 32, 33), (-1.4 / 32, -1), (-0.45 / 32, 0), (5.0, 96),
+                                  (-2.2, -70)])
+def test_constant_network_proposals(b3, q):
+    """A network with zero weights outputs b3: every proposal is q = rint(32 clamp(b3, -3, 3)), and
+    each accepted proposal multiplies the step by 2^(q/32) (labels q/32).  A -> B at rate 1 with
+    h <= 2e-3 < tol accepts every step; shrinking proposals never reach t_end and stop at the
+    step budget."""
+    import oracle
+    from tests.test_oracle_pins import DECAY
+
+    u = mlp.unpack(np.zeros(mlp.N_PARAMS))
+    u["b3"] = np.array([b3])
+    p = mlp.pack(u).astype(np.float32)
+    assert oracle.mlp_forward_c(p, np.zeros(166, np.float32)) == np.float32(b3)
+    out = oracle.integrate_zone_learned(DECAY, np.array([1.0]), np.array([1.0, 1.0]), 2e-3, 1e-5, p,
+                                        opts=oracle.options(max_steps=300), log_capacity=1000)
+    lg = out["log"]
+    want = oracle.ZONE_OK if q >= 0 else oracle.ZONE_MAX_STEPS
+    assert out["status"] == want and out["n_rej"] == 0 and out["n_prop"] >= 2
+    assert (lg["q"] == q).all()
+    ok = ~np.isnan(lg["label"])
+    np.testing.assert_allclose(lg["label"][ok], q / 32.0, rtol=0, atol=1e-12)

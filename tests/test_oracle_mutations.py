@@ -35,20 +35,42 @@ MUTATIONS = {
     "accept_threshold": ("int accept = r <= o->tol;", "int accept = r < 0.5 * o->tol;"),
 }
 
+# mistakes in the learned-controller reference (the part of oracle.c after LEARNED_MARK)
+LEARNED_MUTATIONS = {
+    "learned_no_plain_fallback": ("                step = plain_step;", "                step = h * 0.5;"),
+    "learned_mean_feature_unscaled": ("fmax(ksum / n_species, 1e-300)", "fmax(ksum, 1e-300)"),
+    "learned_label_inverted": ("log2(h / h_prev)", "log2(h_prev / h)"),
+    "learned_bias_dropped": ("        a += b2[j];\n", "\n"),
+    "learned_relu_before_bias": ("        a += b1[j];\n        h1[j] = orc_bf16(a > 0.0 ? a : 0.0);",
+                                 "        h1[j] = orc_bf16(a > 0.0 ? a : 0.0) + b1[j];"),
+    "learned_q_floor": ("q32 = (int32_t)rint(32.0 * fmin(fmax(ov, -3.0), 3.0));",
+                        "q32 = (int32_t)floor(32.0 * fmin(fmax(ov, -3.0), 3.0));"),
+}
+LEARNED_MARK = "Learned step proposer"
+
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
+@pytest.mark.parametrize("name", sorted(MUTATIONS) + sorted(LEARNED_MUTATIONS))
 def test_pins_catch_mutation(name, tmp_path):
-    before, after = MUTATIONS[name]
+    learned = name in LEARNED_MUTATIONS
+    before, after = (LEARNED_MUTATIONS if learned else MUTATIONS)[name]
     dst = tmp_path / "oracle"
     shutil.copytree(os.path.join(ROOT, "oracle"), dst,
                     ignore=shutil.ignore_patterns("*.so", "*.tmp", "__pycache__"))
     src = (dst / "oracle.c").read_text()
-    assert src.count(before) == 1, "mutation site not found: the oracle changed"
-    (dst / "oracle.c").write_text(src.replace(before, after))
+    cut = src.index(LEARNED_MARK)
+    head, tail = src[:cut], src[cut:]
+    if learned:
+        assert tail.count(before) == 1, "mutation site not found: the oracle changed"
+        tail = tail.replace(before, after)
+    else:
+        assert head.count(before) == 1, "mutation site not found: the oracle changed"
+        head = head.replace(before, after)
+    (dst / "oracle.c").write_text(head + tail)
     env = dict(os.environ, PYTHONPATH=f"{tmp_path}{os.pathsep}{ROOT}")
     res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                          os.path.join(ROOT, "tests", "test_mlp_oracle.py")],
                          env=env, cwd=str(tmp_path), capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"no pin failed for mutation {name}:\n{res.stdout[-2000:]}"
     # and the copy really was the one under test
