@@ -278,6 +278,18 @@ asy_status asy_integrate_batch_trace(asy_network *net, const asy_options *opts, 
                                      int64_t capacity, unsigned long long *count, int32_t stride,
                                      int32_t trace_zones, void *stream);
 
+/*
+ * asy_probe_lds_bandwidth: measures the LDS read bandwidth of the current
+ * device, summed over all compute units, in bytes per second.  Every lane
+ * reads width_bytes (8 or 16) per LDS instruction at conflict-free addresses.
+ * The integrator keeps each zone's state in LDS for the whole integration
+ * (section "Implementing the Explicit Asymptotic Algorithm on a CPU-GPU
+ * System"), so this is the bandwidth its roofline is priced against.
+ * Synchronous (runs on the null stream); allocates and frees a small sink
+ * buffer.  ASY_EINVAL for another width or a NULL output.
+ */
+asy_status asy_probe_lds_bandwidth(int32_t width_bytes, double *bytes_per_second);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *asy_last_error(void);
 

@@ -43,6 +43,7 @@ EXPORTS = (
     "asy_mlp_infer",
     "asy_set_mlp",
     "asy_integrate_batch_trace",
+    "asy_probe_lds_bandwidth",
 )
 
 MLP_N_IN = 166
@@ -139,6 +140,8 @@ def lib():
         L.asy_mlp_train_step.argtypes = [P, I32, P, P, F, P, P]
         L.asy_mlp_infer.argtypes = [P, I32, P, P, P]
         L.asy_set_mlp.argtypes = [P, P]
+        L.asy_probe_lds_bandwidth.argtypes = [I32, C.POINTER(C.c_double)]
+        L.asy_probe_lds_bandwidth.restype = I32
         L.asy_integrate_batch_trace.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, P,
                                                 P, P, P, C.c_int64, P, I32, I32, P]
         for name in ("asy_mlp_create", "asy_mlp_set_params", "asy_mlp_get_params", "asy_mlp_forward",
@@ -295,6 +298,13 @@ def asy_autotune(handle, n_species, n_reactions, Y, t_end, dt, T=None, k_zone=No
         C.byref(best))
     _check(st, "asy_autotune")
     return best
+
+
+def asy_probe_lds_bandwidth(width_bytes: int = 16) -> float:
+    """Measured LDS read bandwidth of the current device, bytes per second."""
+    out = C.c_double()
+    _check(lib().asy_probe_lds_bandwidth(int(width_bytes), C.byref(out)), "asy_probe_lds_bandwidth")
+    return out.value
 
 
 def asy_version() -> str:

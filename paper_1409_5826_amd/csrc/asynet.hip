@@ -12,6 +12,7 @@
 
 #include "asynet.h"
 #include "integrate_kernels.h"
+#include "lds_probe.h"
 #include "mlp_kernels.h"
 #include "stratified_kernel.h"
 
@@ -37,7 +38,7 @@ asy_status fail(asy_status st, const std::string &msg)
 
 // Layout of variant 1 for one choice of waves per zone.
 struct StratLayout {
-    int W = 0, lanes = 0, K = 0, C_needed = 0, C = 0, SPL = 0;
+    int W = 0, lanes = 0, C_needed = 0, C = 0, SPL = 0;
     void *dev = nullptr;
     StratNetwork sn{};
     bool ok = false;
@@ -112,13 +113,14 @@ struct StratInstance {
     {W_, SPL_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                    \
     {W_, SPL_, C_, 3, integrate_strat_kernel<W_, SPL_, C_, 2, true, true>}
 const StratInstance kStratInstances[] = {
-    ASY_STRAT(1, 1, 16), ASY_STRAT(1, 1, 32), ASY_STRAT(1, 2, 32), ASY_STRAT(1, 2, 64),
-    ASY_STRAT(1, 3, 64), ASY_STRAT(1, 3, 104), ASY_STRAT(1, 3, 112), ASY_STRAT(1, 4, 64),
-    ASY_STRAT(2, 1, 32), ASY_STRAT(2, 2, 48), ASY_STRAT(2, 2, 64), ASY_STRAT(2, 2, 72),
-    ASY_STRAT(2, 2, 80), ASY_STRAT(2, 3, 64), ASY_STRAT(2, 3, 96), ASY_STRAT(2, 3, 136),
-    ASY_STRAT(4, 1, 32), ASY_STRAT(4, 1, 48), ASY_STRAT(4, 1, 56), ASY_STRAT(4, 1, 64),
-    ASY_STRAT(4, 2, 48), ASY_STRAT(4, 2, 64), ASY_STRAT(4, 2, 80), ASY_STRAT(4, 2, 96),
-    ASY_STRAT_LEARN(1, 1, 16), ASY_STRAT_LEARN(2, 2, 64), ASY_STRAT_LEARN(2, 2, 72),
+    ASY_STRAT(1, 1, 16), ASY_STRAT(1, 1, 32), ASY_STRAT(1, 2, 32), ASY_STRAT(1, 2, 48),
+    ASY_STRAT(1, 3, 48), ASY_STRAT(1, 3, 64), ASY_STRAT(1, 3, 80), ASY_STRAT(1, 3, 96),
+    ASY_STRAT(2, 1, 16), ASY_STRAT(2, 1, 32), ASY_STRAT(2, 2, 32), ASY_STRAT(2, 2, 40),
+    ASY_STRAT(2, 2, 48), ASY_STRAT(2, 2, 64), ASY_STRAT(2, 3, 64), ASY_STRAT(2, 3, 96),
+    ASY_STRAT(2, 3, 104), ASY_STRAT(2, 3, 112),
+    ASY_STRAT(4, 1, 16), ASY_STRAT(4, 1, 32), ASY_STRAT(4, 1, 40), ASY_STRAT(4, 1, 48),
+    ASY_STRAT(4, 2, 48), ASY_STRAT(4, 2, 56), ASY_STRAT(4, 2, 64), ASY_STRAT(4, 2, 80),
+    ASY_STRAT_LEARN(1, 1, 16), ASY_STRAT_LEARN(2, 2, 40), ASY_STRAT_LEARN(2, 2, 48),
 };
 #undef ASY_STRAT
 #undef ASY_STRAT_LEARN
@@ -156,65 +158,63 @@ std::vector<std::vector<Term>> network_rows(int N, int R, const int32_t *r0, con
     return rows;
 }
 
-// Deal the rows out in strata of 64*W lanes, longest rows first.  Leaves
-// L.ok false when no compiled instance can hold the layout.
+// Pack the rows onto 64*W lanes: every row padded to a multiple of 4 terms
+// (at least 4, so that an empty row still writes its 0.0), longest first,
+// each onto the lane with the least work so far (lowest lane on ties).
+// Leaves L.ok false when no compiled instance can hold the layout.
 void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows)
 {
     StratLayout &L = net->strat[w_index(W)];
     L = StratLayout{};
     const int N = net->n_species;
     const int lanes = 64 * W;
+    if ((N + 1) * 8 > 65528 || 2 * N > 2047)
+        return;  // Y byte offsets fit 16 bits; 1 | (out cell << 1) fits 12 bits
+    auto padded = [&](size_t r) { return (int)std::max<size_t>(4, (rows[r].size() + 3) / 4 * 4); };
     std::vector<int> order(rows.size());
     for (size_t r = 0; r < rows.size(); ++r)
         order[r] = (int)r;
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return rows[a].size() > rows[b].size(); });
-    const int K = (int)((rows.size() + lanes - 1) / lanes);
-    std::vector<int32_t> strat_end(K);
-    int slot = 0;
-    for (int k = 0; k < K; ++k) {
-        size_t len = 1;  // every stratum closes at a slot, even when all its rows are empty
-        for (int l = 0; l < lanes; ++l) {
-            const size_t r = (size_t)k * lanes + l;
-            if (r < order.size())
-                len = std::max(len, rows[order[r]].size());
-        }
-        slot += (int)((len + 3) / 4 * 4);  // strata end on multiples of 4 slots
-        strat_end[k] = slot;
+                     [&](int a, int b) { return padded(a) > padded(b); });
+    std::vector<int> load(lanes, 0);
+    std::vector<std::vector<int>> lane_rows(lanes);
+    for (int r : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_rows[l].push_back(r);
+        load[l] += padded(r);
     }
-    if ((N + 1) * 8 > 65535)
-        return;  // byte offsets of Y cells must fit 16 bits
+    const int C_needed = std::max(4, *std::max_element(load.begin(), load.end()));
     L.W = W;
     L.lanes = lanes;
-    L.K = K;
-    L.C_needed = slot;
+    L.C_needed = C_needed;
     L.SPL = (N + lanes - 1) / lanes;
-    const StratInstance *inst = find_strat_instance(W, L.SPL, L.C_needed);
-    if (!inst || L.C_needed > 256)
+    const StratInstance *inst = find_strat_instance(W, L.SPL, C_needed);
+    if (!inst || C_needed > 256)
         return;  // end_mask holds at most 64 blocks of 4 slots
     const int C = inst->C;
     L.C = C;
-    // descriptors hold byte offsets of the two Y cells (cell N = 1.0)
+    // descriptors hold byte offsets of the two Y cells (cell N = 1.0); padding
+    // terms read ONE twice and carry a zero rate
     const uint32_t one = (uint32_t)N * 8u;
     std::vector<uint32_t> desc((size_t)C * lanes, one | (one << 16));
     std::vector<int32_t> rx((size_t)C * lanes, -1);
-    std::vector<int32_t> dst((size_t)K * lanes, 2 * N);
-    int start = 0;
-    for (int k = 0; k < K; ++k) {
-        for (int l = 0; l < lanes; ++l) {
-            const size_t r = (size_t)k * lanes + l;
-            if (r >= order.size())
-                continue;
-            const int row = order[r];
-            dst[(size_t)k * lanes + l] = row;
+    uint64_t end_mask = 0;
+    for (int l = 0; l < lanes; ++l) {
+        int start = 0;
+        for (int row : lane_rows[l]) {
             const auto &terms = rows[row];
             for (size_t e = 0; e < terms.size(); ++e) {
                 const size_t at = (size_t)(start + (int)e) * lanes + l;
                 desc[at] = (uint32_t)terms[e].x * 8u | ((uint32_t)terms[e].y * 8u << 16);
                 rx[at] = terms[e].rx;
             }
+            start += padded(row);
+            const int blk = start / 4 - 1;  // the row ends in this block
+            const uint32_t meta = 1u | ((uint32_t)row << 1);
+            for (int e = 0; e < 4; ++e)
+                desc[(size_t)(4 * blk + e) * lanes + l] |= (meta >> (3 * e)) & 7u;
+            end_mask |= 1ull << blk;
         }
-        start = strat_end[k];
     }
     size_t off = 0;
     auto carve = [&](size_t bytes) {
@@ -223,7 +223,6 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         return o;
     };
     const size_t o_desc = carve(desc.size() * 4), o_rx = carve(rx.size() * 4);
-    const size_t o_end = carve(strat_end.size() * 4), o_dst = carve(dst.size() * 4);
     if (hipMalloc(&L.dev, off) != hipSuccess) {
         L.dev = nullptr;
         return;
@@ -236,21 +235,14 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     };
     put(o_desc, desc.data(), desc.size() * 4);
     put(o_rx, rx.data(), rx.size() * 4);
-    put(o_end, strat_end.data(), strat_end.size() * 4);
-    put(o_dst, dst.data(), dst.size() * 4);
     if (e != hipSuccess)
         return;
     L.sn.n_species = N;
     L.sn.n_reactions = net->n_reactions;
-    L.sn.n_strata = K;
-    L.sn.n_slots = L.C_needed;
-    L.sn.end_mask = 0;
-    for (int k = 0; k < K; ++k)
-        L.sn.end_mask |= 1ull << (strat_end[k] / 4 - 1);
+    L.sn.n_slots = C_needed;
+    L.sn.end_mask = end_mask;
     L.sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc);
     L.sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
-    L.sn.strat_end = reinterpret_cast<const int32_t *>(base + o_end);
-    L.sn.strat_dst = reinterpret_cast<const int32_t *>(base + o_dst);
     L.ok = true;
 }
 
@@ -612,6 +604,60 @@ const char *asy_last_error(void) { return g_last_error.c_str(); }
 
 const char *asy_version(void) { return "asynet 0.2 (gfx950)"; }
 
+asy_status asy_probe_lds_bandwidth(int32_t width_bytes, double *bytes_per_second)
+{
+    g_last_error.clear();
+    if (!bytes_per_second || (width_bytes != 8 && width_bytes != 16))
+        return fail(ASY_EINVAL, "width_bytes must be 8 or 16 and bytes_per_second non-NULL");
+    int dev = 0, n_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int blocks = n_cu * 16;
+    const int passes = width_bytes == 16 ? 4000 : 8000;
+    uint32_t *sink = nullptr;
+    HIP_TRY(hipMalloc(&sink, sizeof(uint32_t) * (size_t)blocks * kProbeThreads));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        (void)hipFree(sink);
+    };
+    auto launch = [&]() {
+        if (width_bytes == 16)
+            lds_read_probe_kernel<uint4><<<blocks, kProbeThreads, 0, nullptr>>>(passes, sink);
+        else
+            lds_read_probe_kernel<uint2><<<blocks, kProbeThreads, 0, nullptr>>>(passes, sink);
+    };
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    const int reps = 5;
+    if (e == hipSuccess) {
+        launch();  // warm-up
+        e = hipEventRecord(e0, nullptr);
+    }
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        launch();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, e0, e1);
+    cleanup();
+    if (e != hipSuccess)
+        return fail(ASY_EDEVICE, std::string("LDS probe: ") + hipGetErrorString(e));
+    const double bytes = (double)reps * blocks * kProbeThreads * (double)passes * kProbeUnroll *
+                         width_bytes;
+    *bytes_per_second = bytes / (ms * 1e-3);
+    return ASY_OK;
+}
+
 asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
 {
     g_last_error.clear();
@@ -775,21 +821,26 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
         for (int W : {1, 2, 4})
             build_strat(net, W, rows);
     }
-    // default launch: variant 1 with the fewest waves per zone whose rates fit
-    // in 80 slots per lane (two waves per SIMD), else the fewest waves with
-    // any instance, else the generic variant 0 (asy_autotune measures instead)
+    // default launch: variant 1 with the least slot work per zone step (slots
+    // per lane x waves), slots beyond 64 per lane weighted 1.25 for the
+    // occupancy their rate registers cost, fewest waves on ties; else the
+    // generic variant 0 (asy_autotune measures instead)
     asy_launch c{};
     c.variant = 0;
     c.threads_per_zone = N <= 64 ? 64 : (N <= 128 ? 128 : 256);
     c.zones_per_group = 1;
-    for (int pass = 0; pass < 2 && c.variant == 0; ++pass) {
+    {
+        double best = 0.0;
         for (int W : {1, 2, 4}) {
             const StratLayout &L = net->strat[w_index(W)];
-            if (L.ok && (pass == 1 || L.C <= 80)) {
+            if (!L.ok)
+                continue;
+            const double cost = (double)L.C * W * (L.C > 64 ? 1.25 : 1.0);
+            if (c.variant == 0 || cost < best) {
+                best = cost;
                 c.variant = 1;
                 c.threads_per_zone = 64 * W;
                 c.zone_order = 1;
-                break;
             }
         }
     }

@@ -1,4 +1,4 @@
-// Variant 1 of the integrator: stratified rows, rates in registers.
+// Variant 1 of the integrator: packed rows, rates in registers.
 //
 // The creation flux F+_i and the depletion rate k_i of Eq. (eq1.1) are sums
 // over the reactions that create or destroy species i.  Each such sum is a
@@ -10,14 +10,18 @@
 // products by 1.0 are exact, and every row is summed from +0.0 in ascending
 // reaction index, exactly as the plain definition does.
 //
-// The host sorts the 2N rows by length and deals them out in strata of
-// 64*W rows, one row per lane.  A lane's column is the concatenation of its
-// rows, each padded to its stratum's length with zero-rate terms (adding +0.0
-// leaves a sum unchanged).  Stratum boundaries are the same slot for every
-// lane, so closing a row is a uniform branch that stores the lane's sum to
-// LDS.  The zone's rates are loaded once into registers (slot s of the lane
-// holds the rate of its term s), so per step the only random LDS traffic is
-// the abundance gathers.  The term descriptors stream from global memory in
+// The host pads every row to a multiple of 4 terms with zero-rate terms
+// (adding +0.0 leaves a sum unchanged) and packs the 2N rows onto the 64*W
+// lanes of a zone's workgroup, longest first, each onto the lane with the
+// least work so far.  A lane's column is the concatenation of its rows, so a
+// row ends at the end of a block of 4 slots, at a different block on each
+// lane.  The lane learns where from its own descriptors: the low 3 bits of
+// the four descriptors of a block carry 12 bits, 1 | (out cell << 1) when the
+// lane's row ends in that block and 0 otherwise; a uniform mask (end_mask,
+// bit b: some lane ends a row in block b) skips the test in the other blocks.
+// The zone's rates are loaded once into registers (slot s of the lane holds
+// the rate of its term s), so per step the only random LDS traffic is the
+// abundance gathers.  The term descriptors stream from global memory in
 // slot-major order and stay in the L1/L2 caches for all zones.
 #pragma once
 
@@ -29,13 +33,11 @@ namespace asynet {
 struct StratNetwork {
     int32_t n_species;
     int32_t n_reactions;
-    int32_t n_strata;
     int32_t n_slots;           // slots used (<= compile-time C)
-    uint64_t end_mask;         // bit b: a stratum ends after block b (slots 4b..4b+3)
-    const uint32_t *desc;      // [C][lanes]: byte offsets of Y[x] | (of Y[y] << 16) in the zone's LDS block
+    uint64_t end_mask;         // bit b: some lane ends a row in block b (slots 4b..4b+3)
+    const uint32_t *desc;      // [C][lanes]: byte offset of Y[x] (+ 3 row-end bits) | byte
+                               // offset of Y[y] << 16, in the zone's LDS block
     const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
-    const int32_t *strat_end;  // [n_strata]: first slot after each stratum
-    const int32_t *strat_dst;  // [n_strata][lanes]: out cell of the row (F+: i, k: N+i, none: 2N)
 };
 
 // Arrhenius rates of every zone, k[z][j] = A_j exp(-E_j / T_z), once per call.
@@ -199,7 +201,6 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
 
     const int N = sn.n_species;
     const int R = sn.n_reactions;
-    const int K = sn.n_strata;
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = tid % kWave;
@@ -306,12 +307,6 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         }
         const uint64_t emask = sn.end_mask;
         constexpr int NB = C / 4;
-        // the lane's row of every stratum (at most 2*SPL strata), kept in registers
-        constexpr int KMAX = 2 * SPL;
-        int dst_zone[KMAX];
-#pragma unroll
-        for (int m = 0; m < KMAX; ++m)
-            dst_zone[m] = (m < K) ? sn.strat_dst[m * LANES + zl] : 2 * N;
         constexpr int kDescAhead = 4;    // descriptor prefetch distance, in blocks of 4 slots
         constexpr int kGatherAhead = GA; // abundance-gather distance, in blocks
         const char *Yb = reinterpret_cast<const char *>(Y);
@@ -339,27 +334,22 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             const bool clipped = step >= t_end - t;
             const double h = clipped ? t_end - t : step;
 
-            // Creation fluxes and depletion rates: one row per lane per stratum.
-            // Strata end on multiples of 4 slots; the blocks that close a
-            // stratum are flagged in end_mask, a uniform kernel argument, so
-            // closing a row is a scalar bit test on a compile-time block index.
+            // Creation fluxes and depletion rates: the lane's packed rows.
+            // Rows end on multiples of 4 slots; blocks where some lane ends a
+            // row are flagged in end_mask, a uniform kernel argument, so the
+            // row-end test is a scalar bit test on a compile-time block index.
             // Software pipeline: while block b is summed, the gathers of blocks
             // up to b+kGatherAhead and the descriptors of block b+kDescAhead are
-            // in flight; the
-            // first kDescAhead blocks' descriptors of a step are loaded during
-            // the previous step's update.
+            // in flight; the first kDescAhead blocks' descriptors of a step are
+            // loaded during the previous step's update.
             {
                 double gx[C], gy[C];
 #pragma unroll
                 for (int s = 0; s < 4 * kGatherAhead && s < C; ++s) {
-                    gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xffffu));
+                    gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xfff8u));
                     gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
                 }
                 double acc = 0.0;
-                int dq_dst[KMAX];
-#pragma unroll
-                for (int m = 0; m < KMAX; ++m)
-                    dq_dst[m] = dst_zone[m];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -367,18 +357,19 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         dq[s] = dsc[s * LANES];
 #pragma unroll
                     for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s) {
-                        gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xffffu));
+                        gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xfff8u));
                         gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
                     }
 #pragma unroll
                     for (int s = 4 * b; s < 4 * b + 4; ++s)
                         acc = acc + (kr[s] * gx[s]) * gy[s];
                     if ((emask >> b) & 1u) {
-                        out[dq_dst[0]] = acc;
-                        acc = 0.0;
-#pragma unroll
-                        for (int m = 0; m + 1 < KMAX; ++m)
-                            dq_dst[m] = dq_dst[m + 1];
+                        const uint32_t meta = (dq[4 * b] & 7u) | ((dq[4 * b + 1] & 7u) << 3) |
+                                              ((dq[4 * b + 2] & 7u) << 6) |
+                                              ((dq[4 * b + 3] & 7u) << 9);
+                        if (meta & 1u)
+                            out[meta >> 1] = acc;
+                        acc = (meta & 1u) ? 0.0 : acc;
                     }
                 }
             }
