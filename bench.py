@@ -8,7 +8,12 @@ state each time.  Inputs are resident in HBM before the timed region.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 Prints one JSON line.  value = accepted zone-steps per second over the K
-timed steps.  roofline: the integrator is bound by LDS traffic; achieved =
+timed steps.  The "learned" object (skipped with --no-learned) compares the
+learned step proposer with the plain controller on held-out zones of the
+150-species constant-rate distribution: traces of the plain integrator on 128
+training zones, 2e5 (features, label) pairs, training on the device, then
+time-to-t_end and final-abundance error (mass-fraction L1 against the plain
+integrator at tol 1e-4) of both forms at several tolerances.  roofline: the integrator is bound by LDS traffic; achieved =
 algorithmic LDS bytes per attempted zone-step x attempted zone-steps per
 launch / average launch time (HIP events on the launch stream); peak = the
 larger of the nominal LDS bandwidth (256 CUs x 128 B/clock x 2.4 GHz) and the
@@ -92,6 +97,9 @@ def main(argv=None):
     ap.add_argument("--launch", default=None, help="JSON dict of asy_launch fields")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch configurations on the workload first")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposer comparison")
+    ap.add_argument("--learned-zones", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args(argv)
@@ -226,9 +234,67 @@ def main(argv=None):
         },
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
     net.close()
+    if not args.no_learned:
+        out["learned"] = learned_leg(args.learned_zones)
+    print(json.dumps(out), flush=True)
     return 0
+
+
+# Algorithmic flops of the network per sample: forward 2 (166*128 + 128*128 + 128);
+# backward (input and weight gradients) twice that.
+MLP_FLOP_PER_SAMPLE = 3 * 2 * (166 * 128 + 128 * 128 + 128)
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3), tol_ref=1e-4) -> dict:
+    """Learned step proposer against the plain controller (time and error at equal tol)."""
+    import numpy as np
+
+    from paper_1409_5826_amd import binding, learned, workloads
+
+    ev = workloads.preset("n150_r1604_const", n_zones=n_eval_zones, seed_offset=1003)
+    tr_wl = workloads.preset("n150_r1604_const", n_zones=128, seed_offset=2003)
+    w = ev.network.weight.astype(np.float64)
+    net = binding.Network(ev.network)
+    try:
+        traces = learned.generate_traces(net, tr_wl.zones, 1e-2, stride=12, capacity=400000)
+        pairs = learned.subsample(traces, 200000, 4005)
+        tr_set, va_set = learned.split_by_zone(pairs, 0.1, 4005)
+        res = learned.train(tr_set, va_set, epochs=20, batch=1024, lr=1e-3, seed=4005)
+        net.set_mlp(res.mlp)
+        ref = learned.integrate(net, ev.zones, tol_ref, False, repeats=1)
+        curves = []
+        for tol in tols:
+            row = {"tol": tol}
+            for form, is_learned in (("plain", False), ("learned", True)):
+                r = learned.integrate(net, ev.zones, tol, is_learned, repeats=1)
+                err = learned.mass_error(r.Y, ref.Y, w)
+                row[form] = {"ms": r.ms, "accepted_per_zone": float(r.n_acc.mean()),
+                             "rejected_per_zone": float(r.n_rej.mean()),
+                             "err_max": float(err.max()), "err_median": float(np.median(err)),
+                             "zones_ok": int((r.status == binding.ZONE_OK).sum())}
+            row["time_ratio_learned_over_plain"] = row["learned"]["ms"] / row["plain"]["ms"]
+            curves.append(row)
+        sps = res.samples / res.seconds if res.seconds > 0 else None
+        out = {
+            "workload": f"n150_r1604_const held-out zones (seed 3005), {n_eval_zones} zones",
+            "train": {"zones": 128, "tol": 1e-2, "pairs": int(len(pairs.zone)),
+                      "train_pairs": int(len(tr_set.zone)), "val_pairs": int(len(va_set.zone)),
+                      "epochs": 20, "batch": 1024,
+                      "train_loss": res.train_loss[-1], "val_loss": res.val_loss[-1],
+                      "val_loss_mean_predictor": res.baseline_val_loss,
+                      "samples_per_s": sps,
+                      "achieved_tflops": None if sps is None else sps * MLP_FLOP_PER_SAMPLE / 1e12,
+                      "peak_tflops_bf16": BF16_DENSE_PEAK_TFLOPS},
+            "error_reference": f"plain integrator at tol {tol_ref:g}",
+            "reference_accepted_per_zone": float(ref.n_acc.mean()),
+            "curves": curves,
+        }
+        res.mlp.close()
+        return out
+    finally:
+        net.close()
 
 
 if __name__ == "__main__":
