@@ -564,7 +564,8 @@ hipError_t mlp_gradient_pass(asy_mlp *m, int n, const float *x, const float *y, 
                                  m->g + kOffW1, nullptr, kMlpHid, nullptr, nullptr, kEpiStore, kMlpHid, s);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(192), 0, s, B, m->g_a1, m->g_a2, m->g_o,
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(kColsumGroups * kMlpHid), 0, s, B, m->g_a1,
+                       m->g_a2, m->g_o,
                        m->h2b, m->g_ob, m->g);
     return hipGetLastError();
 }

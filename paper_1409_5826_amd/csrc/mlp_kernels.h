@@ -211,26 +211,54 @@ __global__ void mlp_out_grad_kernel(int n, const uint16_t *g_ob, const uint16_t 
     }
 }
 
-// dW3[j] = sum_b h2b[b][j] g_ob[b] and the bias gradients (column sums), FP32
-__global__ void mlp_colsum_kernel(int n, const float *g_a1, const float *g_a2, const float *g_o,
-                                  const uint16_t *h2b, const uint16_t *g_ob, float *grad)
+// dW3[j] = sum_b h2b[b][j] g_ob[b] and the bias gradients (column sums), FP32.
+// One workgroup of kColsumGroups x 128 threads: thread (g, j) sums rows
+// b = g, g + kColsumGroups, ... of column j (coalesced across j), then the
+// group partials are added in group order -- a fixed order, so the result is
+// deterministic.  b3's gradient is a sum over the batch reduced the same way.
+constexpr int kColsumGroups = 8;
+
+__global__ void __launch_bounds__(kColsumGroups * kMlpHid)
+mlp_colsum_kernel(int n, const float *g_a1, const float *g_a2, const float *g_o,
+                  const uint16_t *h2b, const uint16_t *g_ob, float *grad)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < kMlpHid) {
-        float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-        for (int b = 0; b < n; ++b) {
-            s1 += g_a1[(size_t)b * kMlpHid + j];
-            s2 += g_a2[(size_t)b * kMlpHid + j];
-            s3 += bf16_bits_to_f32(h2b[(size_t)b * kMlpHid + j]) * bf16_bits_to_f32(g_ob[b]);
+    __shared__ float part[4][kColsumGroups][kMlpHid];
+    const int j = threadIdx.x % kMlpHid;
+    const int g = threadIdx.x / kMlpHid;
+    float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f;
+#pragma unroll 4
+    for (int b = g; b < n; b += kColsumGroups) {
+        const size_t at = (size_t)b * kMlpHid + j;
+        const float go = bf16_bits_to_f32(g_ob[b]);
+        s1 += g_a1[at];
+        s2 += g_a2[at];
+        s3 += bf16_bits_to_f32(h2b[at]) * go;
+    }
+    // b3: column j of a [n / 128 + 1][128] view of g_o
+    for (int b = g * kMlpHid + j; b < n; b += kColsumGroups * kMlpHid)
+        s4 += g_o[b];
+    part[0][g][j] = s1;
+    part[1][g][j] = s2;
+    part[2][g][j] = s3;
+    part[3][g][j] = s4;
+    __syncthreads();
+    if (g == 0) {
+        float t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
+        for (int q = 0; q < kColsumGroups; ++q) {
+            t1 += part[0][q][j];
+            t2 += part[1][q][j];
+            t3 += part[2][q][j];
         }
-        grad[kOffB1 + j] = s1;
-        grad[kOffB2 + j] = s2;
-        grad[kOffW3 + j] = s3;
-    } else if (j == kMlpHid) {
-        float s = 0.0f;
-        for (int b = 0; b < n; ++b)
-            s += g_o[b];
-        grad[kOffB3] = s;
+        grad[kOffB1 + j] = t1;
+        grad[kOffB2 + j] = t2;
+        grad[kOffW3 + j] = t3;
+    }
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int q = 0; q < kColsumGroups; ++q)
+            for (int c = 0; c < kMlpHid; ++c)
+                t += part[3][q][c];
+        grad[kOffB3] = t;
     }
 }
 
@@ -264,96 +292,133 @@ struct MlpDevice {
     float b3;
 };
 
-// One wave evaluates the network for one feature vector x (kMlpInPad floats in
-// LDS, zero padded) and returns o in every lane.  hs: kMlpHid floats of LDS
-// scratch.  Only row 0 of each 16-row A tile carries data.
-__device__ inline float mlp_infer_wave(const MlpDevice &w, const float *x, float *hs, int lane)
+// The W waves of a workgroup evaluate the network for one feature vector x
+// (kMlpInPad floats in LDS, zero padded) together.  Wave w computes the
+// 16-column output tiles w, w + W, ... of each hidden layer and keeps the
+// weights of its next tile in flight while it multiplies the current one; the
+// hidden activations go to LDS (h1, h2: kMlpHid floats each) between the
+// layers, and wave 0 computes the output and leaves it in *o_slot (LDS).
+// sync() is a barrier of the W waves.  Only row 0 of each 16-row A tile
+// carries data.  Every tile sums its k-fragments in the same order whichever
+// wave computes it, so the result does not depend on W.  Returns o in every
+// lane of every wave.
+template <int W, typename Sync>
+__device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, float *h1, float *h2,
+                                        float *o_slot, int lane, int wave, Sync sync)
 {
+    static_assert(8 % W == 0, "the 8 output tiles split evenly over the waves");
+    constexpr int TPW = 8 / W;
     const bool row0 = (lane % 16) == 0;
     const int kg = (lane / 16) * 8;
-    // layer 1: the A fragments (the input row) stay in registers; one output tile of 16
-    // hidden units at a time keeps the weights in flight to one tile's 6 fragments
-    bf16x8 af1[6];
-#pragma unroll
-    for (int kk = 0; kk < 6; ++kk) {
+    auto frag = [&](const float *src, int kk) {
         uint16_t a[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-            a[e] = row0 ? f32_to_bf16_bits(x[32 * kk + kg + e]) : (uint16_t)0;
-        af1[kk] = pack_bf16x8(a);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 1
-    for (int tn = 0; tn < 8; ++tn) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            a[e] = row0 ? f32_to_bf16_bits(src[32 * kk + kg + e]) : (uint16_t)0;
+        return pack_bf16x8(a);
+    };
+    auto ld = [&](const uint16_t *base, int tile_frag) {
+        return *reinterpret_cast<const uint4 *>(base + ((size_t)tile_frag * 64 + lane) * 8);
+    };
+    // layer 1
+    {
+        bf16x8 af[6];
 #pragma unroll
-        for (int kk = 0; kk < 6; ++kk) {
-            const uint4 bw = *reinterpret_cast<const uint4 *>(w.w1s + ((tn * 6 + kk) * 64 + lane) * 8);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af1[kk], __builtin_bit_cast(bf16x8, bw),
-                                                          acc, 0, 0, 0);
-        }
-        // row 0 of the tile sits in lanes 0..15, element 0
-        if (lane < 16) {
-            const float v = acc[0] + w.b1[16 * tn + lane];
-            hs[16 * tn + lane] = bf16_bits_to_f32(f32_to_bf16_bits(v > 0.0f ? v : 0.0f));
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // layer 2: same scheme with 4 fragments of h1
-    bf16x8 af2[4];
+        for (int kk = 0; kk < 6; ++kk)
+            af[kk] = frag(x, kk);
+        uint4 nb[6];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        uint16_t a[8];
+        for (int kk = 0; kk < 6; ++kk)
+            nb[kk] = ld(w.w1s, wave * 6 + kk);
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-            a[e] = row0 ? f32_to_bf16_bits(hs[32 * kk + kg + e]) : (uint16_t)0;
-        af2[kk] = pack_bf16x8(a);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 1
-    for (int tn = 0; tn < 8; ++tn) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = 0; t < TPW; ++t) {
+            const int tn = wave + t * W;
+            uint4 cb[6];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const uint4 bw = *reinterpret_cast<const uint4 *>(w.w2s + ((tn * 4 + kk) * 64 + lane) * 8);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af2[kk], __builtin_bit_cast(bf16x8, bw),
-                                                          acc, 0, 0, 0);
-        }
-        if (lane < 16) {
-            const float v = acc[0] + w.b2[16 * tn + lane];
-            hs[16 * tn + lane] = bf16_bits_to_f32(f32_to_bf16_bits(v > 0.0f ? v : 0.0f));
+            for (int kk = 0; kk < 6; ++kk)
+                cb[kk] = nb[kk];
+            if (t + 1 < TPW) {
+#pragma unroll
+                for (int kk = 0; kk < 6; ++kk)
+                    nb[kk] = ld(w.w1s, (tn + W) * 6 + kk);
+            }
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kk = 0; kk < 6; ++kk)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kk], __builtin_bit_cast(bf16x8, cb[kk]),
+                                                              acc, 0, 0, 0);
+            // row 0 of the tile sits in lanes 0..15, element 0
+            if (lane < 16) {
+                const float v = acc[0] + w.b1[16 * tn + lane];
+                h1[16 * tn + lane] = bf16_bits_to_f32(f32_to_bf16_bits(v > 0.0f ? v : 0.0f));
+            }
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    sync();
+    // layer 2
+    {
+        bf16x8 af[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            af[kk] = frag(h1, kk);
+        uint4 nb[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+            nb[kk] = ld(w.w2s, wave * 4 + kk);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int tn = wave + t * W;
+            uint4 cb[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                cb[kk] = nb[kk];
+            if (t + 1 < TPW) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    nb[kk] = ld(w.w2s, (tn + W) * 4 + kk);
+            }
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kk], __builtin_bit_cast(bf16x8, cb[kk]),
+                                                              acc, 0, 0, 0);
+            if (lane < 16) {
+                const float v = acc[0] + w.b2[16 * tn + lane];
+                h2[16 * tn + lane] = bf16_bits_to_f32(f32_to_bf16_bits(v > 0.0f ? v : 0.0f));
+            }
+        }
+    }
+    sync();
     // layer 3
-    f32x4 acc3 = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (wave == 0) {
+        uint4 b3w[4];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        uint16_t a[8];
+        for (int kk = 0; kk < 4; ++kk)
+            b3w[kk] = ld(w.w3s, kk);
+        f32x4 acc3 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-            a[e] = row0 ? f32_to_bf16_bits(hs[32 * kk + kg + e]) : (uint16_t)0;
-        const uint4 bw = *reinterpret_cast<const uint4 *>(w.w3s + (kk * 64 + lane) * 8);
-        acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pack_bf16x8(a), __builtin_bit_cast(bf16x8, bw),
-                                                       acc3, 0, 0, 0);
+        for (int kk = 0; kk < 4; ++kk)
+            acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(h2, kk), __builtin_bit_cast(bf16x8, b3w[kk]),
+                                                           acc3, 0, 0, 0);
+        if (lane == 0)
+            *o_slot = acc3[0] + w.b3;
     }
-    const float o = acc3[0] + w.b3;  // meaningful in lane 0
-    // every lane has read hs before the caller may reuse it
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, o), 0));
+    sync();
+    return *o_slot;
 }
 
-// Arrange the bf16 weights for mlp_infer_wave (see MlpDevice).
+// Barrier of one wave: LDS operations of a wave complete in order; this only
+// keeps the compiler from moving LDS accesses across it.
+struct WaveSync {
+    __device__ void operator()() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
+// Arrange the bf16 weights for mlp_infer_group (see MlpDevice).
 __global__ void mlp_swizzle_kernel(const float *p, uint16_t *w1s, uint16_t *w2s, uint16_t *w3s)
 {
     const int n1 = 8 * 6 * 64 * 8, n2 = 8 * 4 * 64 * 8, n3 = 4 * 64 * 8;
@@ -382,20 +447,18 @@ __global__ void __launch_bounds__(64)
 mlp_infer_batch_kernel(int n, const float *x, MlpDevice w, float *o)
 {
     __shared__ float xs[kMlpInPad];
-    __shared__ float hs[kMlpHid];
+    __shared__ float h1[kMlpHid];
+    __shared__ float h2[kMlpHid];
+    __shared__ float os;
     const int lane = threadIdx.x;
     for (int b = blockIdx.x; b < n; b += gridDim.x) {
         for (int c = lane; c < kMlpInPad; c += 64)
             xs[c] = c < kMlpIn ? x[(size_t)b * kMlpIn + c] : 0.0f;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const float ob = mlp_infer_wave(w, xs, hs, lane);
+        WaveSync{}();
+        const float ob = mlp_infer_group<1>(w, xs, h1, h2, &os, lane, 0, WaveSync{});
         if (lane == 0)
             o[b] = ob;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        WaveSync{}();
     }
 }
 

@@ -189,7 +189,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
 {
     constexpr bool FEATURES = LEARNED || TRACE;
     __shared__ float feat[FEATURES ? kMlpInPad : 1];
-    __shared__ float hs[FEATURES ? kMlpHid : 1];
+    __shared__ float hs[FEATURES ? 2 * kMlpHid : 1];
     __shared__ double xw_sum[W];
     __shared__ float xw_o;
     static_assert(C % 4 == 0, "slots come in blocks of 4");
@@ -485,15 +485,9 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         int q32 = 0;
                         if constexpr (LEARNED) {
                             if (propose) {
-                                float ov = 0.0f;
-                                if (wave == 0)
-                                    ov = mlp_infer_wave(la.mlp, feat, hs, lane);
-                                if constexpr (W > 1) {
-                                    if (tid == 0)
-                                        xw_o = ov;
-                                    __syncthreads();
-                                    ov = xw_o;
-                                }
+                                const float ov = mlp_infer_group<W>(
+                                    la.mlp, feat, hs, hs + kMlpHid, &xw_o, lane, wave,
+                                    [] { zone_sync<W>(); });
                                 const double oc = fmin(fmax((double)ov, -3.0), 3.0);
                                 q32 = (int)rint(32.0 * oc);
                                 const int qa = (q32 >= 0) ? q32 / 32 : -((31 - q32) / 32);

@@ -63,11 +63,15 @@ def generate_traces(net: binding.Network, zones, tol: float, stride: int = 1,
     torch.cuda.synchronize()
     taken = int(count.item())
     rec = trace[:min(taken, capacity)]
-    ok = torch.isfinite(rec[:, 166])
-    rec = rec[ok]
+    rec = rec[torch.isfinite(rec[:, 166])]
+    # the kernel takes record slots in completion order; sort by (zone, step) so that
+    # everything downstream (subsampling, splits, training) is deterministic
+    zone = rec[:, 168].cpu().numpy().astype(np.int64)
+    n_acc = rec[:, 169].cpu().numpy().astype(np.int64)
+    order = np.lexsort((n_acc, zone))
+    rec = rec.index_select(0, torch.as_tensor(order, device=rec.device))
     return Traces(x=rec[:, :N_FEATURES].contiguous(), y=rec[:, 166].contiguous(),
-                  zone=rec[:, 168].cpu().numpy().astype(np.int64),
-                  n_acc=rec[:, 169].cpu().numpy().astype(np.int64), taken=taken)
+                  zone=zone[order], n_acc=n_acc[order], taken=taken)
 
 
 def _select(tr: Traces, idx: np.ndarray) -> Traces:
