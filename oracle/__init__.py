@@ -76,6 +76,14 @@ def lib():
         L.orc_integrate_batch.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_int32, P, P, P,
                                           P, P, P, P, P, C.POINTER(Options), C.c_int32]
         L.orc_max_threads.restype = C.c_int32
+        L.orc_rhs_f32.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P]
+        L.orc_update_f32.argtypes = [C.c_int32, P, P, P, C.c_float, C.c_float, P]
+        L.orc_integrate_zone_f32.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_double, P,
+                                             C.POINTER(Options), P, P]
+        L.orc_integrate_zone_f32.restype = C.c_int32
+        L.orc_integrate_batch_prec.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P,
+                                               C.c_int32, P, P, P, P, P, P, P, P,
+                                               C.POINTER(Options), C.c_int32]
         L.orc_mlp_forward.argtypes = [P, P]
         L.orc_mlp_forward.restype = C.c_double
         L.orc_mlp_features.argtypes = [C.c_int32, P, P, C.c_double, C.c_double, P]
@@ -167,8 +175,41 @@ def integrate_zone(net, k, Y0, t_end, dt0, opts: Optional[Options] = None, trace
     return out
 
 
-def integrate_batch(net, zones, opts: Optional[Options] = None, n_threads: int = 0):
-    """Integrate every zone of a workloads.Zones batch; returns dict of arrays."""
+def rhs_f32(net, k, Y):
+    """(F+, k_depletion) in float (inputs rounded to float first)."""
+    a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
+    k, Y = np.ascontiguousarray(k, np.float32), np.ascontiguousarray(Y, np.float32)
+    n = net.n_species
+    Fp, kd = np.empty(n, np.float32), np.empty(n, np.float32)
+    lib().orc_rhs_f32(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), _p(Fp), _p(kd))
+    return Fp, kd
+
+
+def update_f32(Y, Fp, kd, h, kappa=1.0):
+    Y, Fp, kd = (np.ascontiguousarray(v, np.float32) for v in (Y, Fp, kd))
+    Yn = np.empty_like(Y)
+    lib().orc_update_f32(len(Y), _p(Y), _p(Fp), _p(kd), float(h), float(kappa), _p(Yn))
+    return Yn
+
+
+def integrate_zone_f32(net, k, Y0, t_end, dt0, opts: Optional[Options] = None):
+    """Integrate one zone in single precision (float state and arithmetic, double time)."""
+    opts = opts or options()
+    a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
+    k = _f64(k)
+    Y = _f64(Y0).copy()
+    dt = np.array([dt0], dtype=np.float64)
+    na, nr = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    st = lib().orc_integrate_zone_f32(net.n_species, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y),
+                                      float(t_end), _p(dt), C.byref(opts), _p(na), _p(nr))
+    return dict(Y=Y, dt=float(dt[0]), n_acc=int(na[0]), n_rej=int(nr[0]), status=int(st))
+
+
+def integrate_batch(net, zones, opts: Optional[Options] = None, n_threads: int = 0,
+                    precision: int = 0):
+    """Integrate every zone of a workloads.Zones batch; returns dict of arrays.
+
+    precision 0: double; 1: single (see integrate_zone_f32)."""
     opts = opts or options()
     a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
     Z, n = zones.Y0.shape
@@ -186,9 +227,9 @@ def integrate_batch(net, zones, opts: Optional[Options] = None, n_threads: int =
         raise ValueError("zones need exactly one of T and k")
     if T is not None and (A is None or E is None):
         raise ValueError("Arrhenius zones need a network with A and E")
-    lib().orc_integrate_batch(n, len(a), _p(a), _p(b), _p(c), _p(A), _p(E), Z, _p(Y), _p(T),
-                              _p(kz), _p(t_end), _p(dt), _p(na), _p(nr), _p(st),
-                              C.byref(opts), int(n_threads))
+    lib().orc_integrate_batch_prec(int(precision), n, len(a), _p(a), _p(b), _p(c), _p(A), _p(E),
+                                   Z, _p(Y), _p(T), _p(kz), _p(t_end), _p(dt), _p(na), _p(nr),
+                                   _p(st), C.byref(opts), int(n_threads))
     return dict(Y=Y, dt=dt, n_acc=na, n_rej=nr, status=st)
 
 

@@ -258,6 +258,176 @@ void orc_integrate_batch(int32_t n_species, int32_t n_reactions, const int32_t *
     }
 }
 
+/* ------------------------------------------------------------------------------------------
+ * Single precision (the paper's single- versus double-precision comparison, section
+ * "Performance for a Single Network", figure singleVsDouble_150).  Reading: the abundances, rates, fluxes, sums, the kappa-
+ * switched update and the change measure r are float; the time bookkeeping (t, the step h,
+ * the step-size rule and the comparison with tol) stays double, since a float t stalls when
+ * t + h rounds back to t.  Rates and abundances are rounded to float once per zone; the
+ * result is widened back to double.  The input checks are those of the double version, on
+ * the double inputs.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Creation fluxes and depletion rates as orc_rhs, in float (ascending reaction index). */
+void orc_rhs_f32(int32_t n_species, int32_t n_reactions, const int32_t *ra, const int32_t *rb,
+                 const int32_t *rc, const float *kf, const float *yf, float *fpf, float *kdf)
+{
+    for (int32_t i = 0; i < n_species; ++i) {
+        fpf[i] = 0.0f;
+        kdf[i] = 0.0f;
+    }
+    for (int32_t j = 0; j < n_reactions; ++j) {
+        const float kj = kf[j];
+        if (rb[j] < 0) {
+            fpf[rc[j]] += kj * yf[ra[j]];
+            kdf[ra[j]] += kj;
+        } else {
+            fpf[rc[j]] += (kj * yf[ra[j]]) * yf[rb[j]];
+            kdf[ra[j]] += kj * yf[rb[j]];
+            kdf[rb[j]] += kj * yf[ra[j]];
+        }
+    }
+}
+
+/* The kappa-switched update as orc_update, in float. */
+void orc_update_f32(int32_t n_species, const float *yf, const float *fpf, const float *kdf,
+                    float hf, float kappaf, float *ynf)
+{
+    for (int32_t i = 0; i < n_species; ++i) {
+        const float khf = kdf[i] * hf;
+        ynf[i] = (khf < kappaf) ? yf[i] + hf * (fpf[i] - kdf[i] * yf[i])
+                                : (yf[i] + hf * fpf[i]) / (1.0f + khf);
+    }
+}
+
+static float orc_change_f32(int32_t n_species, const float *yf, const float *ynf, float floorf_)
+{
+    float rf = 0.0f;
+    for (int32_t i = 0; i < n_species; ++i) {
+        if (!isfinite(ynf[i]))
+            return INFINITY;
+        const float qf = fabsf(ynf[i] - yf[i]) / fmaxf(yf[i], floorf_);
+        rf = (qf > rf) ? qf : rf;
+    }
+    return rf;
+}
+
+/* One zone in single precision; arguments and result as orc_integrate_zone (double arrays). */
+int32_t orc_integrate_zone_f32(int32_t n_species, int32_t n_reactions, const int32_t *a,
+                               const int32_t *b, const int32_t *c, const double *k, double *Y,
+                               double t_end, double *dt, const orc_options *o, int64_t *n_acc_out,
+                               int64_t *n_rej_out)
+{
+    int64_t n_acc = 0, n_rej = 0;
+    *n_acc_out = 0;
+    *n_rej_out = 0;
+    for (int32_t j = 0; j < n_reactions; ++j)
+        if (!isfinite(k[j]))
+            return ORC_ZONE_NONFINITE;
+    for (int32_t i = 0; i < n_species; ++i)
+        if (!isfinite(Y[i]))
+            return ORC_ZONE_NONFINITE;
+    if (!isfinite(t_end) || !isfinite(*dt))
+        return ORC_ZONE_NONFINITE;
+    for (int32_t j = 0; j < n_reactions; ++j)
+        if (k[j] < 0.0)
+            return ORC_ZONE_BAD_INPUT;
+    for (int32_t i = 0; i < n_species; ++i)
+        if (Y[i] < 0.0)
+            return ORC_ZONE_BAD_INPUT;
+    if (t_end < 0.0 || !(*dt > 0.0))
+        return ORC_ZONE_BAD_INPUT;
+
+    float *kf = malloc(sizeof(float) * (size_t)n_reactions);
+    float *Yf = malloc(sizeof(float) * (size_t)n_species);
+    float *Fp = malloc(sizeof(float) * (size_t)n_species);
+    float *kd = malloc(sizeof(float) * (size_t)n_species);
+    float *Yn = malloc(sizeof(float) * (size_t)n_species);
+    for (int32_t j = 0; j < n_reactions; ++j)
+        kf[j] = (float)k[j];
+    for (int32_t i = 0; i < n_species; ++i)
+        Yf[i] = (float)Y[i];
+    const float kappa = (float)o->kappa, y_floor = (float)o->y_floor;
+    /* the controller of orc_integrate_zone, on the double value of the float change measure */
+    double tt = 0.0, trial = *dt;
+    int32_t status = ORC_ZONE_OK;
+    for (;;) {
+        if (tt >= t_end) {
+            status = ORC_ZONE_OK;
+            break;
+        }
+        if (n_acc + n_rej >= o->max_steps) {
+            status = ORC_ZONE_MAX_STEPS;
+            break;
+        }
+        const int last = trial >= t_end - tt;
+        const double hh = last ? t_end - tt : trial;
+        orc_rhs_f32(n_species, n_reactions, a, b, c, kf, Yf, Fp, kd);
+        orc_update_f32(n_species, Yf, Fp, kd, (float)hh, kappa, Yn);
+        const double rr = (double)orc_change_f32(n_species, Yf, Yn, y_floor);
+        if (rr <= o->tol) {
+            memcpy(Yf, Yn, sizeof(float) * (size_t)n_species);
+            n_acc++;
+            tt = last ? t_end : tt + hh;
+            if (last == 0)
+                trial = hh * (rr == 0.0 ? o->grow_max : fmin(o->safety * o->tol / rr, o->grow_max));
+        } else {
+            n_rej++;
+            trial = hh * (isinf(rr) ? o->shrink_min : fmax(o->safety * o->tol / rr, o->shrink_min));
+            if (trial < o->dt_min) {
+                status = ORC_ZONE_DT_UNDERFLOW;
+                break;
+            }
+        }
+    }
+    for (int32_t i = 0; i < n_species; ++i)
+        Y[i] = (double)Yf[i];
+    free(kf);
+    free(Yf);
+    free(Fp);
+    free(kd);
+    free(Yn);
+    *dt = trial;
+    *n_acc_out = n_acc;
+    *n_rej_out = n_rej;
+    return status;
+}
+
+/* orc_integrate_batch in single precision (precision 1) or double (precision 0). */
+void orc_integrate_batch_prec(int32_t precision, int32_t n_species, int32_t n_reactions,
+                              const int32_t *a, const int32_t *b, const int32_t *c,
+                              const double *A, const double *E, int32_t n_zones, double *Y,
+                              const double *T, const double *k_zone, const double *t_end,
+                              double *dt, int64_t *n_acc, int64_t *n_rej, int32_t *status,
+                              const orc_options *o, int32_t n_threads)
+{
+    if (precision == 0) {
+        orc_integrate_batch(n_species, n_reactions, a, b, c, A, E, n_zones, Y, T, k_zone, t_end,
+                            dt, n_acc, n_rej, status, o, n_threads);
+        return;
+    }
+#ifdef _OPENMP
+    int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
+    for (int32_t z = 0; z < n_zones; ++z) {
+        double *k = malloc(sizeof(double) * (size_t)n_reactions);
+        if (k_zone) {
+            memcpy(k, k_zone + (size_t)z * n_reactions, sizeof(double) * (size_t)n_reactions);
+        } else if (!isfinite(T[z])) {
+            for (int32_t j = 0; j < n_reactions; ++j) k[j] = NAN;
+        } else if (!(T[z] > 0.0)) {
+            for (int32_t j = 0; j < n_reactions; ++j) k[j] = -1.0;
+        } else {
+            orc_rates_arrhenius(n_reactions, A, E, T[z], k);
+        }
+        status[z] = orc_integrate_zone_f32(n_species, n_reactions, a, b, c, k,
+                                           Y + (size_t)z * n_species, t_end[z], dt + z, o,
+                                           n_acc + z, n_rej + z);
+        free(k);
+    }
+}
+
 int32_t orc_max_threads(void)
 {
 #ifdef _OPENMP

@@ -33,6 +33,12 @@ MUTATIONS = {
     "change_against_new_state": ("fabs(Yn[i] - Y[i]) / fmax(Y[i], y_floor)",
                                  "fabs(Yn[i] - Y[i]) / fmax(Yn[i], y_floor)"),
     "accept_threshold": ("int accept = r <= o->tol;", "int accept = r < 0.5 * o->tol;"),
+    # single precision
+    "f32_euler_sign": ("yf[i] + hf * (fpf[i] - kdf[i] * yf[i])", "yf[i] + hf * (fpf[i] + kdf[i] * yf[i])"),
+    "f32_asymptotic_denominator": ("/ (1.0f + khf)", "/ (1.0f + kdf[i])"),
+    "f32_partner_index": ("kdf[ra[j]] += kj * yf[rb[j]];", "kdf[ra[j]] += kj * yf[ra[j]];"),
+    "f32_change_against_new_state": ("fmaxf(yf[i], floorf_)", "fmaxf(ynf[i], floorf_)"),
+    "f32_state_kept_double": ("        Yf[i] = (float)Y[i];", "        Yf[i] = (float)(Y[i] * 1.0000001);"),
 }
 
 # mistakes in the learned-controller reference (the part of oracle.c after LEARNED_MARK)
@@ -70,7 +76,8 @@ def test_pins_catch_mutation(name, tmp_path):
     env = dict(os.environ, PYTHONPATH=f"{tmp_path}{os.pathsep}{ROOT}")
     res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                           os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                          os.path.join(ROOT, "tests", "test_mlp_oracle.py")],
+                          os.path.join(ROOT, "tests", "test_mlp_oracle.py"),
+                          os.path.join(ROOT, "tests", "test_oracle_f32.py")],
                          env=env, cwd=str(tmp_path), capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"no pin failed for mutation {name}:\n{res.stdout[-2000:]}"
     # and the copy really was the one under test
