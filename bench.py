@@ -73,15 +73,18 @@ def profiled_traffic(workload: str):
         return None
 
 
-def algorithmic_bytes_per_zone_step(n_species: int, n_reactions: int, n_destruction: int) -> int:
-    """LDS bytes one attempted step of one zone must move (FP64 = 8 B, index = 2 B).
+def algorithmic_bytes_per_zone_step(n_species: int, n_reactions: int, n_destruction: int,
+                                    value_bytes: int = 8) -> int:
+    """LDS bytes one attempted step of one zone must move (value = 8 B in double, 4 B in
+    single precision; index = 2 B).
 
     Per reaction: read k_j, write the flux, read it back with its product
-    index (26 B).  Per destruction incidence: gather the partner abundance
-    with its index, write the partial rate, read it back (26 B).  Per
-    species: five reads/writes of Y, F+, k, Yn (40 B).
+    index (3 values + 2 B).  Per destruction incidence: gather the partner
+    abundance with its index, write the partial rate, read it back (3 values
+    + 2 B).  Per species: five reads/writes of Y, F+, k, Yn (5 values).
     """
-    return 26 * (n_reactions + n_destruction) + 40 * n_species
+    v = value_bytes
+    return (3 * v + 2) * (n_reactions + n_destruction) + 5 * v * n_species
 
 
 def main(argv=None):
@@ -97,6 +100,8 @@ def main(argv=None):
     ap.add_argument("--launch", default=None, help="JSON dict of asy_launch fields")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch configurations on the workload first")
+    ap.add_argument("--no-f32", action="store_true",
+                    help="skip the single-precision measurement of the same workload")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposer comparison")
     ap.add_argument("--learned-zones", type=int, default=64)
@@ -234,11 +239,45 @@ def main(argv=None):
         },
         "cpu_baseline": cpu,
     }
+    if not args.no_f32:
+        out["f32"] = f32_leg(net, buf, Y0, dt0, stream, args.steps, b_step_fn=lambda: (
+            algorithmic_bytes_per_zone_step(n.n_species, n.n_reactions, n.n_destruction, 4)),
+            peak=peak)
     net.close()
     if not args.no_learned:
         out["learned"] = learned_leg(args.learned_zones)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def f32_leg(net, buf, Y0, dt0, stream, steps, b_step_fn, peak) -> dict:
+    """The same workload integrated in single precision (HIP events, same launch)."""
+    import numpy as np
+    import torch
+
+    from paper_1409_5826_amd import binding
+
+    opts = binding.options_default(precision=binding.PREC_F32)
+    times = []
+    for i in range(steps + 1):
+        buf["Y"].copy_(Y0)
+        buf["dt"].copy_(dt0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        net.integrate(buf, opts, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i > 0:  # the first run warms up
+            times.append(e0.elapsed_time(e1))
+    acc = int(buf["n_accepted"].sum().item())
+    att = acc + int(buf["n_rejected"].sum().item())
+    ms = float(np.mean(times))
+    b32 = b_step_fn()
+    achieved = b32 * att / (ms / 1e3) / 1e9
+    return {"time_to_t_end_ms": ms, "zone_steps_per_s": acc / (ms / 1e3),
+            "accepted_zone_steps": acc, "rejected_zone_steps": att - acc,
+            "bytes_per_zone_step": b32, "achieved_GBs": achieved, "frac": achieved / peak,
+            "launch": net.get_launch()}
 
 
 # Algorithmic flops of the network per sample: forward 2 (166*128 + 128*128 + 128);

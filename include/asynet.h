@@ -115,8 +115,19 @@ typedef struct {
     double dt_min;     /* 1e-20 */
     int64_t max_steps; /* attempted steps per zone; 10,000,000 */
     int32_t controller;/* ASY_CTRL_PLAIN */
-    int32_t reserved;  /* must be 0 */
+    int32_t precision; /* ASY_PREC_F64 */
 } asy_options;
+
+/*
+ * Arithmetic of the integration (the paper compares single- and double-
+ * precision integration, section "Performance for a Single Network").
+ * ASY_PREC_F32: abundances, rates, fluxes, sums, the update and the change
+ * measure in float, rounded from the double inputs once per zone and widened
+ * back on output; time, the step size and its rule stay double.  Launch
+ * variant 1 and the plain controller only (ASY_ENOTSUP otherwise, also for
+ * asy_integrate_batch_trace).
+ */
+enum { ASY_PREC_F64 = 0, ASY_PREC_F32 = 1 };
 
 /* Launch configuration of the integrator kernel (see asy_autotune). */
 typedef struct {
@@ -193,7 +204,10 @@ asy_status asy_set_launch(asy_network *net, const asy_launch *cfg);
 /*
  * Time candidate launch configurations on copies of the first sample_zones
  * zones of the given batch (same arguments as asy_integrate_batch, left
- * unmodified) and keep the fastest.  Synchronous.  best: host, out, may be NULL.
+ * unmodified) and keep the fastest: variant 1 with 1, 2 and 4 waves per zone
+ * and both zone orders, and variant 0 with 128 and 256 threads (double
+ * precision only).  Candidates run in opts->precision with the plain
+ * controller.  Synchronous.  best: host, out, may be NULL.
  */
 asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sample_zones,
                         const double *Y, const double *T, const double *k_zone,

@@ -21,6 +21,7 @@ ASY_OK, ASY_EINVAL, ASY_ENOMEM, ASY_EDEVICE, ASY_ENOTSUP, ASY_ESTATE = 0, -1, -2
 ZONE_OK, ZONE_MAX_STEPS, ZONE_DT_UNDERFLOW, ZONE_NONFINITE, ZONE_BAD_INPUT = range(5)
 RATES_PER_ZONE, RATES_ARRHENIUS = 0, 1
 CTRL_PLAIN, CTRL_LEARNED = 0, 1
+PREC_F64, PREC_F32 = 0, 1
 
 # Every symbol include/asynet.h declares.
 EXPORTS = (
@@ -82,7 +83,7 @@ class asy_options(C.Structure):
         ("dt_min", C.c_double),
         ("max_steps", C.c_int64),
         ("controller", C.c_int32),
-        ("reserved", C.c_int32),
+        ("precision", C.c_int32),
     ]
 
 

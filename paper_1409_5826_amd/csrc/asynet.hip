@@ -39,6 +39,8 @@ asy_status fail(asy_status st, const std::string &msg)
 // Layout of variant 1 for one choice of waves per zone.
 struct StratLayout {
     int W = 0, lanes = 0, C_needed = 0, C = 0, SPL = 0;
+    bool ok32 = false;    // the single-precision descriptors exist (N <= 2046)
+    StratNetwork sn32{};  // the same layout with descriptors for float cells
     void *dev = nullptr;
     StratNetwork sn{};
     bool ok = false;
@@ -101,13 +103,16 @@ namespace {
 using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *, const int32_t *,
                              LearnArgs);
 
-// mode: 0 plain controller, 1 plain with trace, 2 learned, 3 learned with trace
+// mode: 0 plain controller, 1 plain with trace, 2 learned, 3 learned with trace,
+//       4 plain controller in single precision
 struct StratInstance {
     int W, SPL, C, mode;
     StratKernel fn;
 };
 
 #define ASY_STRAT(W_, SPL_, C_) {W_, SPL_, C_, 0, integrate_strat_kernel<W_, SPL_, C_, 2, false, false>}
+#define ASY_STRAT_F32(W_, SPL_, C_)                                                             \
+    {W_, SPL_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, 2, false, false, float>}
 #define ASY_STRAT_LEARN(W_, SPL_, C_)                                                           \
     {W_, SPL_, C_, 1, integrate_strat_kernel<W_, SPL_, C_, 2, false, true>},                    \
     {W_, SPL_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                    \
@@ -121,8 +126,16 @@ const StratInstance kStratInstances[] = {
     ASY_STRAT(4, 1, 16), ASY_STRAT(4, 1, 32), ASY_STRAT(4, 1, 40), ASY_STRAT(4, 1, 48),
     ASY_STRAT(4, 2, 48), ASY_STRAT(4, 2, 56), ASY_STRAT(4, 2, 64), ASY_STRAT(4, 2, 80),
     ASY_STRAT_LEARN(1, 1, 16), ASY_STRAT_LEARN(2, 2, 40), ASY_STRAT_LEARN(2, 2, 48),
+    ASY_STRAT_F32(1, 1, 16), ASY_STRAT_F32(1, 1, 32), ASY_STRAT_F32(1, 2, 32), ASY_STRAT_F32(1, 2, 48),
+    ASY_STRAT_F32(1, 3, 48), ASY_STRAT_F32(1, 3, 64), ASY_STRAT_F32(1, 3, 80), ASY_STRAT_F32(1, 3, 96),
+    ASY_STRAT_F32(2, 1, 16), ASY_STRAT_F32(2, 1, 32), ASY_STRAT_F32(2, 2, 32), ASY_STRAT_F32(2, 2, 40),
+    ASY_STRAT_F32(2, 2, 48), ASY_STRAT_F32(2, 2, 64), ASY_STRAT_F32(2, 3, 64), ASY_STRAT_F32(2, 3, 96),
+    ASY_STRAT_F32(2, 3, 104), ASY_STRAT_F32(2, 3, 112),
+    ASY_STRAT_F32(4, 1, 16), ASY_STRAT_F32(4, 1, 32), ASY_STRAT_F32(4, 1, 40), ASY_STRAT_F32(4, 1, 48),
+    ASY_STRAT_F32(4, 2, 48), ASY_STRAT_F32(4, 2, 56), ASY_STRAT_F32(4, 2, 64), ASY_STRAT_F32(4, 2, 80),
 };
 #undef ASY_STRAT
+#undef ASY_STRAT_F32
 #undef ASY_STRAT_LEARN
 
 const StratInstance *find_strat_instance(int W, int SPL, int C_needed, int mode = 0)
@@ -195,8 +208,9 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L.C = C;
     // descriptors hold byte offsets of the two Y cells (cell N = 1.0); padding
     // terms read ONE twice and carry a zero rate
-    const uint32_t one = (uint32_t)N * 8u;
+    const uint32_t one = (uint32_t)N * 8u, one32 = (uint32_t)N * 4u;
     std::vector<uint32_t> desc((size_t)C * lanes, one | (one << 16));
+    std::vector<uint32_t> desc32((size_t)C * lanes, one32 | (one32 << 16));
     std::vector<int32_t> rx((size_t)C * lanes, -1);
     uint64_t end_mask = 0;
     for (int l = 0; l < lanes; ++l) {
@@ -206,16 +220,20 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
             for (size_t e = 0; e < terms.size(); ++e) {
                 const size_t at = (size_t)(start + (int)e) * lanes + l;
                 desc[at] = (uint32_t)terms[e].x * 8u | ((uint32_t)terms[e].y * 8u << 16);
+                desc32[at] = (uint32_t)terms[e].x * 4u | ((uint32_t)terms[e].y * 4u << 16);
                 rx[at] = terms[e].rx;
             }
             start += padded(row);
             const int blk = start / 4 - 1;  // the row ends in this block
             const uint32_t meta = 1u | ((uint32_t)row << 1);
-            for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < 4; ++e) {
                 desc[(size_t)(4 * blk + e) * lanes + l] |= (meta >> (3 * e)) & 7u;
+                desc32[(size_t)(4 * blk + e) * lanes + l] |= ((meta >> (3 * e)) & 7u) << 13;
+            }
             end_mask |= 1ull << blk;
         }
     }
+    const bool ok32 = (N + 1) * 4 <= 8191;  // float byte addresses stay below bit 13
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
@@ -223,6 +241,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         return o;
     };
     const size_t o_desc = carve(desc.size() * 4), o_rx = carve(rx.size() * 4);
+    const size_t o_desc32 = carve(desc32.size() * 4);
     if (hipMalloc(&L.dev, off) != hipSuccess) {
         L.dev = nullptr;
         return;
@@ -235,6 +254,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     };
     put(o_desc, desc.data(), desc.size() * 4);
     put(o_rx, rx.data(), rx.size() * 4);
+    put(o_desc32, desc32.data(), desc32.size() * 4);
     if (e != hipSuccess)
         return;
     L.sn.n_species = N;
@@ -243,6 +263,9 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L.sn.end_mask = end_mask;
     L.sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc);
     L.sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
+    L.sn32 = L.sn;
+    L.sn32.desc = reinterpret_cast<const uint32_t *>(base + o_desc32);
+    L.ok32 = ok32;
     L.ok = true;
 }
 
@@ -353,7 +376,8 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
         if (c.groups_per_cu > 0)
             grid = std::min(grid, c.groups_per_cu * net->n_cu);
         hipLaunchKernelGGL(inst->fn, dim3(grid), dim3(c.threads_per_zone * zpg),
-                           lds_bytes_variant1(net, zpg), s, L.sn, o, za, rates, order, la);
+                           lds_bytes_variant1(net, zpg), s, mode == 4 ? L.sn32 : L.sn, o, za, rates,
+                           order, la);
         return hipGetLastError();
     }
     int grid = za.n_zones;
@@ -393,8 +417,8 @@ asy_status validate_options(const asy_options *o)
         return fail(ASY_EINVAL, "max_steps must be >= 0");
     if (o->controller != ASY_CTRL_PLAIN && o->controller != ASY_CTRL_LEARNED)
         return fail(ASY_EINVAL, "unknown controller");
-    if (o->reserved != 0)
-        return fail(ASY_EINVAL, "asy_options.reserved must be 0");
+    if (o->precision != ASY_PREC_F64 && o->precision != ASY_PREC_F32)
+        return fail(ASY_EINVAL, "unknown precision");
     return ASY_OK;
 }
 
@@ -598,7 +622,7 @@ void asy_options_default(asy_options *o)
     o->dt_min = 1e-20;
     o->max_steps = 10000000;
     o->controller = ASY_CTRL_PLAIN;
-    o->reserved = 0;
+    o->precision = ASY_PREC_F64;
 }
 
 const char *asy_last_error(void) { return g_last_error.c_str(); }
@@ -923,8 +947,19 @@ asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n
         return fail(ASY_EINVAL, "trace needs buffers, 0 <= capacity < 2^31, stride >= 1, "
                                 "trace_zones >= 0");
     const bool learned = o.controller == ASY_CTRL_LEARNED;
-    const int mode = (learned ? 2 : 0) + (trace ? 1 : 0);
-    if (mode != 0) {
+    int mode = (learned ? 2 : 0) + (trace ? 1 : 0);
+    if (o.precision == ASY_PREC_F32) {
+        if (mode != 0)
+            return fail(ASY_ENOTSUP, "single precision supports the plain controller without trace");
+        if (net->launch.variant != 1)
+            return fail(ASY_ENOTSUP, "single precision needs launch variant 1");
+        const StratLayout &L = net->strat[w_index(net->launch.threads_per_zone / 64)];
+        if (!L.ok32 || !find_strat_instance(L.W, L.SPL, L.C, 4))
+            return fail(ASY_ENOTSUP, "no single-precision kernel instance for this network and "
+                                     "launch configuration");
+        mode = 4;
+    }
+    if (mode != 0 && mode != 4) {
         if (net->n_species > ASY_MLP_N_IN - 4)
             return fail(ASY_ENOTSUP, "learned controller and trace take at most 162 species");
         if (learned && !net->has_mlp)
@@ -1028,17 +1063,23 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
         cleanup();
         return fail(ASY_EDEVICE, "autotune: hipEventCreate failed");
     }
+    // candidates: variant 1 for each W with both zone orders, and variant 0 (double only);
+    // the plain controller is timed whatever opts->controller says
+    const int mode = o.precision == ASY_PREC_F32 ? 4 : 0;
     std::vector<asy_launch> cands;
     for (int W : {1, 2, 4}) {
-        if (!net->strat[w_index(W)].ok)
+        const StratLayout &L = net->strat[w_index(W)];
+        if (!L.ok || (mode == 4 && (!L.ok32 || !find_strat_instance(W, L.SPL, L.C, 4))))
             continue;
-        asy_launch c{1, 64 * W, 1, 0, net->launch.use_graph, 0};
-        if (validate_launch(net, &c) == ASY_OK)
-            cands.push_back(c);
+        for (int zo : {1, 0}) {
+            asy_launch c{1, 64 * W, 1, 0, net->launch.use_graph, zo};
+            if (validate_launch(net, &c) == ASY_OK)
+                cands.push_back(c);
+        }
     }
     for (int nt : {128, 256}) {
         asy_launch c{0, nt, 1, 0, net->launch.use_graph, 0};
-        if (validate_launch(net, &c) == ASY_OK)
+        if (mode == 0 && validate_launch(net, &c) == ASY_OK)
             cands.push_back(c);
     }
     g_last_error.clear();
@@ -1055,7 +1096,7 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
             if (hipMemcpy(wY, Y, nY * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
                 hipMemcpy(wdt, dt, (size_t)Z * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
                 hipEventRecord(e0, nullptr) != hipSuccess ||
-                launch_all(net, c, to_dev(o), za, nullptr) != hipSuccess ||
+                launch_all(net, c, to_dev(o), za, nullptr, mode) != hipSuccess ||
                 hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 st = fail(ASY_EDEVICE, "autotune: a candidate launch failed");

@@ -101,6 +101,22 @@ __device__ inline double wave_max_dpp(double v)
     return __hiloint2double(hi, lo);
 }
 
+// The same for float.
+__device__ inline float wave_max_dpp(float v)
+{
+#define ASY_DPP_MAX_STEP_F32(ctrl, rmask)                                                       \
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), \
+                                                            ctrl, rmask, 0xf, false)))
+    ASY_DPP_MAX_STEP_F32(0x111, 0xf);
+    ASY_DPP_MAX_STEP_F32(0x112, 0xf);
+    ASY_DPP_MAX_STEP_F32(0x114, 0xf);
+    ASY_DPP_MAX_STEP_F32(0x118, 0xf);
+    ASY_DPP_MAX_STEP_F32(0x142, 0xa);
+    ASY_DPP_MAX_STEP_F32(0x143, 0xc);
+#undef ASY_DPP_MAX_STEP_F32
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 #define ASY_DPP_SUM_STEP(v, ctrl, rmask)                                                       \
     do {                                                                                       \
         const int lo_ = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, rmask, 0xf, false); \

@@ -171,23 +171,43 @@ __device__ inline void zone_sync()
     }
 }
 
+// Element type of the zone's cells.  A descriptor's low half is the LDS byte
+// address of Y[x] plus 3 of the 12 row-end bits of its block: in the low 3
+// bits for double cells (byte addresses are multiples of 8), in bits 13..15
+// for float cells (byte addresses are multiples of 4 and below 8192).
+template <typename T>
+struct CellCode;
+template <>
+struct CellCode<double> {
+    static constexpr uint32_t kAddr = 0xfff8u;
+    __device__ static uint32_t bits(uint32_t d) { return d & 7u; }
+};
+template <>
+struct CellCode<float> {
+    static constexpr uint32_t kAddr = 0x1fffu;
+    __device__ static uint32_t bits(uint32_t d) { return (d >> 13) & 7u; }
+};
+
 // A workgroup of W waves integrates one zone at a time.
-// Waves per SIMD the register budget allows: the zone's rates take 2*C
-// registers and the pipelines, addresses and update about 128 more, out of
-// 512 per SIMD lane.
-template <int C>
+// Waves per SIMD the register budget allows: the zone's rates take C
+// registers per 4 bytes of T and the pipelines, addresses and update about
+// 128 (double) or 96 (float) more, out of 512 per SIMD lane.
+template <int C, typename T = double>
 constexpr int strat_waves_per_eu()
 {
-    return 512 / (2 * C + 128) < 1 ? 1 : (512 / (2 * C + 128) > 8 ? 8 : 512 / (2 * C + 128));
+    constexpr int regs = C * (int)(sizeof(T) / 4) + (sizeof(T) == 8 ? 128 : 96);
+    return 512 / regs < 1 ? 1 : (512 / regs > 8 ? 8 : 512 / regs);
 }
 
-template <int W, int SPL, int C, int GA = 2, bool LEARNED = false, bool TRACE = false>
+template <int W, int SPL, int C, int GA = 2, bool LEARNED = false, bool TRACE = false,
+          typename T = double>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
-                               amdgpu_waves_per_eu(strat_waves_per_eu<C>())))
+                               amdgpu_waves_per_eu(strat_waves_per_eu<C, T>())))
 integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates,
                        const int32_t *order, LearnArgs la)
 {
     constexpr bool FEATURES = LEARNED || TRACE;
+    static_assert(!FEATURES || sizeof(T) == 8, "learned controller and trace in double only");
     __shared__ float feat[FEATURES ? kMlpInPad : 1];
     __shared__ float hs[FEATURES ? 2 * kMlpHid : 1];
     __shared__ double xw_sum[W];
@@ -205,8 +225,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     const int wave = tid / kWave;
     const int lane = tid % kWave;
     const int zl = tid;  // lane within the zone
-    double *Y = lds;
-    double *out = Y + (N + 1);
+    T *Y = reinterpret_cast<T *>(lds);
+    T *out = Y + (N + 1);
 
     for (;;) {
         // ---- next zone: a wave-wide atomic, lane 0's ticket broadcast by a cross-lane read
@@ -236,7 +256,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         int flag = 0;  // bit 0: non-finite input, bit 1: out-of-domain input
         // rates: gathered once per zone from the [zone][reaction] table (the
         // per-zone input, or the table the Arrhenius rate kernel filled)
-        double kr[C];
+        T kr[C];
         {
             const double *kz = rates + (size_t)z * R;
 #pragma unroll
@@ -250,7 +270,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                     else if (kj < 0.0)
                         flag |= 2;
                 }
-                kr[s] = kj;
+                kr[s] = (T)kj;
             }
         }
         const double *Yz = za.Y + (size_t)z * N;
@@ -259,7 +279,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             const int i = zl + m * LANES;
             if (i < N) {
                 const double y = Yz[i];
-                Y[i] = y;
+                Y[i] = (T)y;
                 if (!isfinite(y))
                     flag |= 1;
                 else if (y < 0.0)
@@ -267,7 +287,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             }
         }
         if (zl == 0)
-            Y[N] = 1.0;
+            Y[N] = (T)1.0;
         if (!isfinite(t_end) || !isfinite(dt0))
             flag |= 1;
         else if (t_end < 0.0 || !(dt0 > 0.0))
@@ -343,13 +363,13 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             // in flight; the first kDescAhead blocks' descriptors of a step are
             // loaded during the previous step's update.
             {
-                double gx[C], gy[C];
+                T gx[C], gy[C];
 #pragma unroll
                 for (int s = 0; s < 4 * kGatherAhead && s < C; ++s) {
-                    gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xfff8u));
-                    gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
+                    gx[s] = *reinterpret_cast<const T *>(Yb + (dq[s] & CellCode<T>::kAddr));
+                    gy[s] = *reinterpret_cast<const T *>(Yb + (dq[s] >> 16));
                 }
-                double acc = 0.0;
+                T acc = (T)0.0;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -357,19 +377,20 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         dq[s] = dsc[s * LANES];
 #pragma unroll
                     for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s) {
-                        gx[s] = *reinterpret_cast<const double *>(Yb + (dq[s] & 0xfff8u));
-                        gy[s] = *reinterpret_cast<const double *>(Yb + (dq[s] >> 16));
+                        gx[s] = *reinterpret_cast<const T *>(Yb + (dq[s] & CellCode<T>::kAddr));
+                        gy[s] = *reinterpret_cast<const T *>(Yb + (dq[s] >> 16));
                     }
 #pragma unroll
                     for (int s = 4 * b; s < 4 * b + 4; ++s)
                         acc = acc + (kr[s] * gx[s]) * gy[s];
                     if ((emask >> b) & 1u) {
-                        const uint32_t meta = (dq[4 * b] & 7u) | ((dq[4 * b + 1] & 7u) << 3) |
-                                              ((dq[4 * b + 2] & 7u) << 6) |
-                                              ((dq[4 * b + 3] & 7u) << 9);
+                        using Code = CellCode<T>;
+                        const uint32_t meta = Code::bits(dq[4 * b]) | (Code::bits(dq[4 * b + 1]) << 3) |
+                                              (Code::bits(dq[4 * b + 2]) << 6) |
+                                              (Code::bits(dq[4 * b + 3]) << 9);
                         if (meta & 1u)
                             out[meta >> 1] = acc;
-                        acc = (meta & 1u) ? 0.0 : acc;
+                        acc = (meta & 1u) ? (T)0.0 : acc;
                     }
                 }
             }
@@ -385,33 +406,34 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             zone_sync<W>();
 
             // kappa-switched update of the lane's species and the change measure
-            double yn[SPL];
-            double rloc = 0.0;
+            T yn[SPL];
+            T rloc = (T)0.0;
             bool bad = false;
+            const T hT = (T)h, kappaT = (T)o.kappa, floorT = (T)o.y_floor;
 #pragma unroll
             for (int m = 0; m < SPL; ++m) {
                 const int i = zl + m * LANES;
-                yn[m] = 0.0;
+                yn[m] = (T)0.0;
                 if (i < N) {
-                    const double fp = out[i];
-                    const double kd = out[N + i];
-                    const double y = Y[i];
-                    const double kh = kd * h;
-                    double v;
-                    if (kh < o.kappa)
-                        v = y + h * (fp - kd * y);     // forward Euler
+                    const T fp = out[i];
+                    const T kd = out[N + i];
+                    const T y = Y[i];
+                    const T kh = kd * hT;
+                    T v;
+                    if (kh < kappaT)
+                        v = y + hT * (fp - kd * y);          // forward Euler
                     else
-                        v = (y + h * fp) / (1.0 + kh);  // asymptotic form
+                        v = (y + hT * fp) / ((T)1.0 + kh);   // asymptotic form
                     yn[m] = v;
                     if (!isfinite(v))
                         bad = true;
                     else
-                        rloc = fmax(rloc, fabs(v - y) / fmax(y, o.y_floor));
+                        rloc = fmax(rloc, fabs(v - y) / fmax(y, floorT));
                 }
             }
             if (bad)
-                rloc = INFINITY;
-            double r = wave_max_dpp(rloc);
+                rloc = (T)INFINITY;
+            double r = (double)wave_max_dpp(rloc);
             if constexpr (W > 1) {
                 if (lane == 0)
                     xw_r[wave] = r;
@@ -551,7 +573,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         for (int m = 0; m < SPL; ++m) {
             const int i = zl + m * LANES;
             if (i < N)
-                Yo[i] = Y[i];
+                Yo[i] = (double)Y[i];
         }
         if (zl == 0) {
             za.dt[z] = step;
