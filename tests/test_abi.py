@@ -32,7 +32,8 @@ def test_options_default():
     o = binding.options_default()
     assert (o.kappa, o.tol, o.y_floor, o.grow_max, o.safety, o.shrink_min, o.dt_min) == \
         (1.0, 0.01, 1e-10, 2.0, 0.9, 0.1, 1e-20)
-    assert o.max_steps == 10_000_000 and o.controller == binding.CTRL_PLAIN and o.reserved == 0
+    assert o.max_steps == 10_000_000 and o.controller == binding.CTRL_PLAIN
+    assert o.precision == binding.PREC_F64
 
 
 def _create(**kw):
