@@ -110,9 +110,11 @@ struct StratInstance {
     StratKernel fn;
 };
 
-#define ASY_STRAT(W_, SPL_, C_) {W_, SPL_, C_, 0, integrate_strat_kernel<W_, SPL_, C_, 2, false, false>}
+#define ASY_STRAT(W_, SPL_, C_)                                                                 \
+    {W_, SPL_, C_, 0, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_>(), false, false>}
 #define ASY_STRAT_F32(W_, SPL_, C_)                                                             \
-    {W_, SPL_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, 2, false, false, float>}
+    {W_, SPL_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_, float>(), false,   \
+                                           false, float>}
 #define ASY_STRAT_LEARN(W_, SPL_, C_)                                                           \
     {W_, SPL_, C_, 1, integrate_strat_kernel<W_, SPL_, C_, 2, false, true>},                    \
     {W_, SPL_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                    \

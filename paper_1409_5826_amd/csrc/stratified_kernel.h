@@ -189,14 +189,31 @@ struct CellCode<float> {
 };
 
 // A workgroup of W waves integrates one zone at a time.
-// Waves per SIMD the register budget allows: the zone's rates take C
-// registers per 4 bytes of T and the pipelines, addresses and update about
-// 128 (double) or 96 (float) more, out of 512 per SIMD lane.
+// Waves per SIMD (the register budget the compiler gets): the zone's rates
+// take C registers per 4 bytes of T, the pipelines, addresses and update the
+// rest.  Occupancy outweighs some spilling at up to 40 slots (3 waves in
+// double, 4 in float) and up to 56 slots in float (3 waves), as measured on
+// the 150- and 365-species workloads; otherwise the budget leaves about 128
+// (double) or 96 (float) registers beside the rates.
 template <int C, typename T = double>
 constexpr int strat_waves_per_eu()
 {
+    if (sizeof(T) == 8 && C <= 40)
+        return 3;
+    if (sizeof(T) == 4 && C <= 40)
+        return 4;
+    if (sizeof(T) == 4 && C <= 56)
+        return 3;
     constexpr int regs = C * (int)(sizeof(T) / 4) + (sizeof(T) == 8 ? 128 : 96);
     return 512 / regs < 1 ? 1 : (512 / regs > 8 ? 8 : 512 / regs);
+}
+
+// Abundance-gather distance in blocks: 1 where the budget above is tight in
+// double precision, else 2.
+template <int C, typename T = double>
+constexpr int strat_gather_ahead()
+{
+    return (sizeof(T) == 8 && C <= 40) ? 1 : 2;
 }
 
 template <int W, int SPL, int C, int GA = 2, bool LEARNED = false, bool TRACE = false,
