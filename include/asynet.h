@@ -304,6 +304,32 @@ asy_status asy_integrate_batch_trace(asy_network *net, const asy_options *opts, 
  */
 asy_status asy_probe_lds_bandwidth(int32_t width_bytes, double *bytes_per_second);
 
+/*
+ * asy_integrate_schedule: n_steps consecutive hydro steps of the operator-split
+ * scheme (section "Operator-Split Integration Timesteps"), queued on stream
+ * without host synchronisation.  In step s every zone z is integrated over
+ * dt_hydro[s][z] (device [n_steps][n_zones]) with the temperature T[s][z]
+ * (device [n_steps][n_zones], Arrhenius networks) or its constant rates k_zone
+ * (device [n_zones][n_reactions]), starting from the abundances and the trial
+ * step the previous step left in Y and dt (in/out, as asy_integrate_batch).
+ * The copy-out of the section "Implementing the Explicit Asymptotic Algorithm
+ * on a CPU-GPU System" lists the energy released by the integration; with q
+ * (device [n_species], energy per unit abundance of each species) it is
+ *   energy[s][z] = sum_i q_i (Y_i after step s - Y_i before step s),
+ * summed in ascending species index (energy: device [n_steps][n_zones], or
+ * NULL; q may then be NULL).  n_accepted / n_rejected (device [n_zones], out)
+ * sum over the steps; zone_status holds each zone's first non-OK status, else
+ * ASY_ZONE_OK.  Later steps still integrate a zone after a failed step, from
+ * what that step left.  Options and launch as asy_integrate_batch (no trace);
+ * the launch configuration's graph replay is not used.  ASY_EINVAL for
+ * n_steps < 1, energy without q, or missing arrays.
+ */
+asy_status asy_integrate_schedule(asy_network *net, const asy_options *opts, int32_t n_zones,
+                                  int32_t n_steps, double *Y, const double *T, const double *k_zone,
+                                  const double *dt_hydro, double *dt, const double *q,
+                                  double *energy, int64_t *n_accepted, int64_t *n_rejected,
+                                  int32_t *zone_status, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *asy_last_error(void);
 

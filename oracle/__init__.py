@@ -76,6 +76,9 @@ def lib():
         L.orc_integrate_batch.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_int32, P, P, P,
                                           P, P, P, P, P, C.POINTER(Options), C.c_int32]
         L.orc_max_threads.restype = C.c_int32
+        L.orc_integrate_schedule.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P,
+                                             C.c_int32, C.c_int32, P, P, P, P, P, P, P, P, P, P,
+                                             C.POINTER(Options), C.c_int32]
         L.orc_rhs_f32.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P]
         L.orc_update_f32.argtypes = [C.c_int32, P, P, P, C.c_float, C.c_float, P]
         L.orc_integrate_zone_f32.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_double, P,
@@ -286,3 +289,27 @@ def integrate_zone_learned(net, k, Y0, t_end, dt0, params=None, opts: Optional[O
         out["log"] = dict(q=lq[:n].copy() if learned else None, feat=lf[:n].copy(),
                           label=ll[:n].copy(), n_acc=ln[:n].copy())
     return out
+
+
+def integrate_schedule(net, zones, sched, opts: Optional[Options] = None, n_threads: int = 0,
+                       precision: int = 0, with_energy: bool = True):
+    """Run the operator-split steps of a workloads.Schedule; returns dict of arrays
+    (Y, dt, n_acc, n_rej, status, energy [n_steps, Z])."""
+    opts = opts or options()
+    a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
+    Z, n = zones.Y0.shape
+    S = sched.n_steps
+    Y = _f64(zones.Y0).copy()
+    dt = _f64(zones.dt0).copy()
+    na, nr = np.zeros(Z, np.int64), np.zeros(Z, np.int64)
+    st = np.zeros(Z, np.int32)
+    energy = np.zeros((S, Z)) if with_energy else None
+    T = None if sched.T is None else _f64(sched.T)
+    kz = None if zones.k is None else _f64(zones.k)
+    A = None if net.A is None else _f64(net.A)
+    E = None if net.E is None else _f64(net.E)
+    lib().orc_integrate_schedule(int(precision), n, len(a), _p(a), _p(b), _p(c), _p(A), _p(E), Z, S,
+                                 _p(Y), _p(T), _p(kz), _p(_f64(sched.dt_hydro)), _p(dt),
+                                 _p(_f64(sched.q)), _p(energy), _p(na), _p(nr), _p(st),
+                                 C.byref(opts), int(n_threads))
+    return dict(Y=Y, dt=dt, n_acc=na, n_rej=nr, status=st, energy=energy)

@@ -428,6 +428,61 @@ void orc_integrate_batch_prec(int32_t precision, int32_t n_species, int32_t n_re
     }
 }
 
+/*
+ * The operator-split coupling (section "Operator-Split Integration Timesteps"): n_steps
+ * consecutive hydro steps.  In step s every zone z is integrated over dt_hydro[s][z] with
+ * the temperature T[s][z] (Arrhenius rates, evaluated once per step) or its constant rates,
+ * starting from the abundances and the trial step the previous step left.  The copy-out of
+ * the CPU--GPU section lists the energy released over the integration; with an energy per
+ * unit abundance q_i for each species (caller-supplied) it is the change of sum_i q_i Y_i,
+ *   energy[s][z] = sum_i q_i (Y_i after step s - Y_i before step s), ascending i.
+ * n_acc / n_rej sum over the steps; status is the first non-OK status of a zone, else OK.
+ * energy may be NULL.
+ */
+void orc_integrate_schedule(int32_t precision, int32_t n_species, int32_t n_reactions,
+                            const int32_t *a, const int32_t *b, const int32_t *c, const double *A,
+                            const double *E, int32_t n_zones, int32_t n_steps, double *Y,
+                            const double *T, const double *k_zone, const double *dt_hydro,
+                            double *dt, const double *q, double *energy, int64_t *n_acc,
+                            int64_t *n_rej, int32_t *status, const orc_options *o, int32_t n_threads)
+{
+    const size_t NZ = (size_t)n_zones * n_species;
+    double *before = malloc(sizeof(double) * (NZ ? NZ : 1));
+    int64_t *acc_s = malloc(sizeof(int64_t) * (n_zones ? n_zones : 1));
+    int64_t *rej_s = malloc(sizeof(int64_t) * (n_zones ? n_zones : 1));
+    int32_t *st_s = malloc(sizeof(int32_t) * (n_zones ? n_zones : 1));
+    for (int32_t z = 0; z < n_zones; ++z) {
+        n_acc[z] = 0;
+        n_rej[z] = 0;
+        status[z] = ORC_ZONE_OK;
+    }
+    for (int32_t s = 0; s < n_steps; ++s) {
+        memcpy(before, Y, sizeof(double) * NZ);
+        orc_integrate_batch_prec(precision, n_species, n_reactions, a, b, c, A, E, n_zones, Y,
+                                 T ? T + (size_t)s * n_zones : NULL, k_zone,
+                                 dt_hydro + (size_t)s * n_zones, dt, acc_s, rej_s, st_s, o,
+                                 n_threads);
+        for (int32_t z = 0; z < n_zones; ++z) {
+            n_acc[z] += acc_s[z];
+            n_rej[z] += rej_s[z];
+            if (status[z] == ORC_ZONE_OK)
+                status[z] = st_s[z];
+            if (energy) {
+                double e = 0.0;
+                for (int32_t i = 0; i < n_species; ++i) {
+                    const size_t at = (size_t)z * n_species + i;
+                    e += q[i] * (Y[at] - before[at]);
+                }
+                energy[(size_t)s * n_zones + z] = e;
+            }
+        }
+    }
+    free(before);
+    free(acc_s);
+    free(rej_s);
+    free(st_s);
+}
+
 int32_t orc_max_threads(void)
 {
 #ifdef _OPENMP

@@ -45,6 +45,7 @@ EXPORTS = (
     "asy_set_mlp",
     "asy_integrate_batch_trace",
     "asy_probe_lds_bandwidth",
+    "asy_integrate_schedule",
 )
 
 MLP_N_IN = 166
@@ -141,6 +142,8 @@ def lib():
         L.asy_mlp_train_step.argtypes = [P, I32, P, P, F, P, P]
         L.asy_mlp_infer.argtypes = [P, I32, P, P, P]
         L.asy_set_mlp.argtypes = [P, P]
+        L.asy_integrate_schedule.argtypes = [P, C.POINTER(asy_options), I32, I32, P, P, P, P, P, P,
+                                             P, P, P, P, P]
         L.asy_probe_lds_bandwidth.argtypes = [I32, C.POINTER(C.c_double)]
         L.asy_probe_lds_bandwidth.restype = I32
         L.asy_integrate_batch_trace.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, P,
@@ -272,6 +275,31 @@ def asy_integrate_batch_trace(handle, n_species, n_reactions, Y, t_end, dt, n_ac
     _check(st, "asy_integrate_batch_trace")
 
 
+def asy_integrate_schedule(handle, n_species, n_reactions, Y, dt_hydro, dt, n_accepted,
+                           n_rejected, zone_status, T=None, k_zone=None, q=None, energy=None,
+                           opts: Optional[asy_options] = None, stream=None):
+    """Queue len(dt_hydro) operator-split hydro steps (device [n_steps, Z] schedule arrays)."""
+    import torch
+
+    Z = int(Y.shape[0])
+    S = int(dt_hydro.shape[0])
+    args = [
+        _dev_ptr(Y, torch.float64, (Z, n_species), "Y"),
+        _dev_ptr(T, torch.float64, (S, Z), "T"),
+        _dev_ptr(k_zone, torch.float64, (Z, n_reactions), "k_zone"),
+        _dev_ptr(dt_hydro, torch.float64, (S, Z), "dt_hydro"),
+        _dev_ptr(dt, torch.float64, (Z,), "dt"),
+        _dev_ptr(q, torch.float64, (n_species,), "q"),
+        _dev_ptr(energy, torch.float64, (S, Z), "energy"),
+        _dev_ptr(n_accepted, torch.int64, (Z,), "n_accepted"),
+        _dev_ptr(n_rejected, torch.int64, (Z,), "n_rejected"),
+        _dev_ptr(zone_status, torch.int32, (Z,), "zone_status"),
+    ]
+    st = lib().asy_integrate_schedule(handle, None if opts is None else C.byref(opts), Z, S,
+                                      *args, _stream_ptr(stream))
+    _check(st, "asy_integrate_schedule")
+
+
 def asy_get_launch(handle) -> asy_launch:
     c = asy_launch()
     _check(lib().asy_get_launch(handle, C.byref(c)), "asy_get_launch")
@@ -364,6 +392,23 @@ class Network:
                                   buf["zone_status"], trace, count, stride,
                                   Z if trace_zones is None else trace_zones, T=buf["T"],
                                   k_zone=buf["k_zone"], opts=opts, stream=stream)
+
+    def integrate_schedule(self, buf, sched, opts=None, stream=None, with_energy=True):
+        """Run a workloads.Schedule on the zones in buf; returns the energy [n_steps, Z] (device)."""
+        import torch
+
+        dev = buf["Y"].device
+        S, Z = sched.dt_hydro.shape
+        dt_h = torch.as_tensor(sched.dt_hydro, dtype=torch.float64, device=dev).contiguous()
+        T = None if sched.T is None else torch.as_tensor(sched.T, dtype=torch.float64,
+                                                         device=dev).contiguous()
+        q = torch.as_tensor(sched.q, dtype=torch.float64, device=dev)
+        energy = torch.zeros((S, Z), dtype=torch.float64, device=dev) if with_energy else None
+        asy_integrate_schedule(self.handle, self.n_species, self.n_reactions, buf["Y"], dt_h,
+                               buf["dt"], buf["n_accepted"], buf["n_rejected"], buf["zone_status"],
+                               T=T, k_zone=buf["k_zone"], q=q, energy=energy, opts=opts,
+                               stream=stream)
+        return energy
 
     def set_mlp(self, mlp: "Mlp"):
         asy_set_mlp(self.handle, mlp)

@@ -71,6 +71,8 @@ struct asy_network {
     float *key_buf = nullptr;   // scheduling keys of one call, [zones]
     int32_t *order_buf = nullptr; // scheduling order of one call, [zones]
     size_t order_buf_zones = 0;
+    void *sched_block = nullptr;  // asy_integrate_schedule: before-abundances and step counters
+    size_t sched_zones = 0;
     asy_launch launch{};
     hipStream_t capture_stream = nullptr;
     GraphCache graph;
@@ -898,6 +900,8 @@ void asy_network_destroy(asy_network *net)
         (void)hipFree(net->mlp_block);
     if (net->rate_buf)
         (void)hipFree(net->rate_buf);
+    if (net->sched_block)
+        (void)hipFree(net->sched_block);
     if (net->key_buf)
         (void)hipFree(net->key_buf);
     if (net->order_buf)
@@ -927,27 +931,10 @@ asy_status asy_set_launch(asy_network *net, const asy_launch *cfg)
 namespace {
 
 // Shared argument checks and launch of asy_integrate_batch and asy_integrate_batch_trace.
-asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n_zones, double *Y,
-                            const double *T, const double *k_zone, const double *t_end, double *dt,
-                            int64_t *n_accepted, int64_t *n_rejected, int32_t *zone_status,
-                            void *stream, bool trace, LearnArgs la)
+// Kernel family of a call: 0 plain, 1 plain + trace, 2 learned, 3 learned + trace, 4 plain in
+// single precision; ASY_ENOTSUP / ASY_ESTATE when the network or launch cannot run it.
+asy_status resolve_mode(const asy_network *net, const asy_options &o, bool trace, int *mode_out)
 {
-    g_last_error.clear();
-    if (!net)
-        return fail(ASY_EINVAL, "net must be non-NULL");
-    asy_options o;
-    asy_options_default(&o);
-    if (opts)
-        o = *opts;
-    asy_status st = validate_options(&o);
-    if (st != ASY_OK)
-        return st;
-    if (n_zones < 0)
-        return fail(ASY_EINVAL, "n_zones must be >= 0");
-    if (trace && (!la.trace || !la.count || la.capacity < 0 || la.capacity > INT32_MAX ||
-                  la.stride < 1 || la.trace_zones < 0))
-        return fail(ASY_EINVAL, "trace needs buffers, 0 <= capacity < 2^31, stride >= 1, "
-                                "trace_zones >= 0");
     const bool learned = o.controller == ASY_CTRL_LEARNED;
     int mode = (learned ? 2 : 0) + (trace ? 1 : 0);
     if (o.precision == ASY_PREC_F32) {
@@ -973,6 +960,35 @@ asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n
             return fail(ASY_ENOTSUP, "no learned/trace kernel instance for this network and "
                                      "launch configuration");
     }
+    *mode_out = mode;
+    return ASY_OK;
+}
+
+asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n_zones, double *Y,
+                            const double *T, const double *k_zone, const double *t_end, double *dt,
+                            int64_t *n_accepted, int64_t *n_rejected, int32_t *zone_status,
+                            void *stream, bool trace, LearnArgs la)
+{
+    g_last_error.clear();
+    if (!net)
+        return fail(ASY_EINVAL, "net must be non-NULL");
+    asy_options o;
+    asy_options_default(&o);
+    if (opts)
+        o = *opts;
+    asy_status st = validate_options(&o);
+    if (st != ASY_OK)
+        return st;
+    if (n_zones < 0)
+        return fail(ASY_EINVAL, "n_zones must be >= 0");
+    if (trace && (!la.trace || !la.count || la.capacity < 0 || la.capacity > INT32_MAX ||
+                  la.stride < 1 || la.trace_zones < 0))
+        return fail(ASY_EINVAL, "trace needs buffers, 0 <= capacity < 2^31, stride >= 1, "
+                                "trace_zones >= 0");
+    int mode = 0;
+    st = resolve_mode(net, o, trace, &mode);
+    if (st != ASY_OK)
+        return st;
     if (n_zones == 0)
         return ASY_OK;
     if (!Y || !t_end || !dt || !n_accepted || !n_rejected || !zone_status)
@@ -1018,6 +1034,78 @@ asy_status asy_integrate_batch_trace(asy_network *net, const asy_options *opts, 
     la.trace_zones = trace_zones;
     return integrate_common(net, opts, n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected,
                             zone_status, stream, true, la);
+}
+
+asy_status asy_integrate_schedule(asy_network *net, const asy_options *opts, int32_t n_zones,
+                                  int32_t n_steps, double *Y, const double *T, const double *k_zone,
+                                  const double *dt_hydro, double *dt, const double *q,
+                                  double *energy, int64_t *n_accepted, int64_t *n_rejected,
+                                  int32_t *zone_status, void *stream)
+{
+    g_last_error.clear();
+    if (!net)
+        return fail(ASY_EINVAL, "net must be non-NULL");
+    asy_options o;
+    asy_options_default(&o);
+    if (opts)
+        o = *opts;
+    asy_status st = validate_options(&o);
+    if (st != ASY_OK)
+        return st;
+    if (n_zones < 0 || n_steps < 1)
+        return fail(ASY_EINVAL, "n_zones must be >= 0 and n_steps >= 1");
+    if (energy && !q)
+        return fail(ASY_EINVAL, "the energy release needs q");
+    int mode = 0;
+    st = resolve_mode(net, o, false, &mode);
+    if (st != ASY_OK)
+        return st;
+    if (n_zones == 0)
+        return ASY_OK;
+    if (!Y || !dt_hydro || !dt || !n_accepted || !n_rejected || !zone_status)
+        return fail(ASY_EINVAL,
+                    "Y, dt_hydro, dt, n_accepted, n_rejected, zone_status must be non-NULL");
+    if (net->rate_form == ASY_RATES_ARRHENIUS) {
+        if (!T || k_zone)
+            return fail(ASY_EINVAL, "Arrhenius networks take T and no k_zone");
+    } else if (!k_zone || T) {
+        return fail(ASY_EINVAL, "per-zone-rate networks take k_zone and no T");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(net->device));
+    st = ensure_call_bufs(net, net->launch, n_zones, s);
+    if (st != ASY_OK)
+        return st;
+    // per-step counters and the abundances before the step (grow-only scratch)
+    const size_t nY = (size_t)n_zones * net->n_species;
+    if (net->sched_zones < (size_t)n_zones) {
+        HIP_TRY(hipStreamSynchronize(s));
+        (void)hipFree(net->sched_block);
+        net->sched_block = nullptr;
+        net->sched_zones = 0;
+        HIP_TRY(hipMalloc(&net->sched_block, (size_t)n_zones * (8 + 8 + 4 + 8 * net->n_species)));
+        net->sched_zones = (size_t)n_zones;
+    }
+    char *b = static_cast<char *>(net->sched_block);
+    double *before = reinterpret_cast<double *>(b);
+    int64_t *acc_s = reinterpret_cast<int64_t *>(b + nY * 8);
+    int64_t *rej_s = acc_s + n_zones;
+    int32_t *st_s = reinterpret_cast<int32_t *>(rej_s + n_zones);
+    const DevOptions dev = to_dev(o);
+    const int blocks = std::max(1, std::min((n_zones + 255) / 256, net->n_cu * 4));
+    for (int32_t step = 0; step < n_steps; ++step) {
+        if (energy)
+            HIP_TRY(hipMemcpyAsync(before, Y, nY * 8, hipMemcpyDeviceToDevice, s));
+        ZoneArgs za{n_zones, Y, T ? T + (size_t)step * n_zones : nullptr, k_zone,
+                    dt_hydro + (size_t)step * n_zones, dt, acc_s, rej_s, st_s, net->queue};
+        HIP_TRY(launch_all(net, net->launch, dev, za, s, mode));
+        hipLaunchKernelGGL(schedule_step_kernel, dim3(blocks), dim3(256), 0, s, n_zones,
+                           net->n_species, step == 0 ? 1 : 0, acc_s, rej_s, st_s, n_accepted,
+                           n_rejected, zone_status, Y, before, q,
+                           energy ? energy + (size_t)step * n_zones : nullptr);
+        HIP_TRY(hipGetLastError());
+    }
+    return ASY_OK;
 }
 
 asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sample_zones,

@@ -346,4 +346,28 @@ integrate_group_kernel(DevNetwork net, DevOptions o, ZoneArgs za)
     }
 }
 
+// One hydro step of a schedule, after the integration: add the step's counters to the
+// totals (set them on the first step), keep the first non-OK status, and the energy
+// released, sum_i q_i (Y_i - before_i) in ascending species order (one thread per zone).
+__global__ void __launch_bounds__(256)
+schedule_step_kernel(int32_t n_zones, int32_t n_species, int first, const int64_t *acc_s,
+                     const int64_t *rej_s, const int32_t *st_s, int64_t *n_acc, int64_t *n_rej,
+                     int32_t *status, const double *Y, const double *before, const double *q,
+                     double *energy)
+{
+    for (int z = blockIdx.x * blockDim.x + threadIdx.x; z < n_zones; z += gridDim.x * blockDim.x) {
+        n_acc[z] = (first ? 0 : n_acc[z]) + acc_s[z];
+        n_rej[z] = (first ? 0 : n_rej[z]) + rej_s[z];
+        status[z] = (first || status[z] == kZoneOk) ? st_s[z] : status[z];
+        if (energy) {
+            const double *y = Y + (size_t)z * n_species;
+            const double *y0 = before + (size_t)z * n_species;
+            double e = 0.0;
+            for (int i = 0; i < n_species; ++i)
+                e += q[i] * (y[i] - y0[i]);
+            energy[z] = e;
+        }
+    }
+}
+
 }  // namespace asynet

@@ -35,6 +35,8 @@ __all__ = [
     "Network",
     "Zones",
     "Workload",
+    "Schedule",
+    "make_schedule",
     "make_network",
     "make_zones",
     "preset",
@@ -316,6 +318,39 @@ def _n365_arrh(n_zones=1024, e_window=None):
                     f"(log10 A in 2..12, E in {e_lo:g}..{e_hi:g}), T log-uniform 1..4 per zone, "
                     "t_end 1 s",
                     extra={"E_window": (e_lo, e_hi)})
+
+
+@dataclass
+class Schedule:
+    """Inputs of an operator-split sequence of hydro steps for a batch of zones."""
+
+    T: Optional[np.ndarray]   # float64 [n_steps, Z] temperature per step (Arrhenius zones)
+    dt_hydro: np.ndarray      # float64 [n_steps, Z] interval of each step
+    q: np.ndarray             # float64 [N] energy per unit abundance of each species
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.dt_hydro.shape[0])
+
+
+def make_schedule(net: Network, zones: Zones, n_steps: int, seed: int,
+                  T_swing: float = 0.1) -> Schedule:
+    """Split each zone's interval into n_steps equal hydro steps; Arrhenius zones get a
+    temperature path T_z (1 + T_swing sin(2 pi (s / n_steps + phase_z))), seeded phases; the
+    energy coefficients are a smooth function of the weight, q_i = w_i (8 - 9 w_i^(-1/3)),
+    plus 1 % seeded noise."""
+    rng = _rng(seed)
+    Z = zones.n_zones
+    dt_h = np.tile(zones.t_end / n_steps, (n_steps, 1))
+    T = None
+    if zones.T is not None:
+        phase = rng.uniform(0.0, 1.0, size=Z)
+        s = np.arange(n_steps)[:, None]
+        T = zones.T[None, :] * (1.0 + T_swing * np.sin(2.0 * np.pi * (s / n_steps + phase[None, :])))
+    w = net.weight.astype(np.float64)
+    q = w * (8.0 - 9.0 * w ** (-1.0 / 3.0)) * (1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=net.n_species))
+    return Schedule(T=None if T is None else np.ascontiguousarray(T),
+                    dt_hydro=np.ascontiguousarray(dt_h), q=np.ascontiguousarray(q))
 
 
 PRESETS = {
