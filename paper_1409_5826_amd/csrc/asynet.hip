@@ -39,6 +39,7 @@ asy_status fail(asy_status st, const std::string &msg)
 // Layout of variant 1 for one choice of waves per zone.
 struct StratLayout {
     int W = 0, lanes = 0, C_needed = 0, C = 0, SPL = 0;
+    int n_part = 0;       // partial-sum cells of split rows
     bool ok32 = false;    // the single-precision descriptors exist (N <= 2046)
     StratNetwork sn32{};  // the same layout with descriptors for float cells
     void *dev = nullptr;
@@ -175,11 +176,14 @@ std::vector<std::vector<Term>> network_rows(int N, int R, const int32_t *r0, con
     return rows;
 }
 
+constexpr int kSplitAbove = 64;  // rows with more terms are summed in chunks
+constexpr int kSplitChunk = 32;  // terms per chunk of a split row
+
 // Pack the rows onto 64*W lanes: every row padded to a multiple of 4 terms
 // (at least 4, so that an empty row still writes its 0.0), longest first,
 // each onto the lane with the least work so far (lowest lane on ties).
 // Leaves L.ok false when no compiled instance can hold the layout.
-void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows)
+void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows_in)
 {
     StratLayout &L = net->strat[w_index(W)];
     L = StratLayout{};
@@ -187,6 +191,43 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     const int lanes = 64 * W;
     if ((N + 1) * 8 > 65528 || 2 * N > 2047)
         return;  // Y byte offsets fit 16 bits; 1 | (out cell << 1) fits 12 bits
+    // Rows of more than kSplitAbove terms (hub species: far longer than the lanes' average
+    // work) are split into chunks of kSplitChunk consecutive terms; chunk k of a split row is
+    // a row of its own summing into partial cell 2N + 1 + p, and the kernel adds a split
+    // row's partials in chunk order.  The rule does not depend on the launch, so every
+    // launch configuration computes the same sums.
+    std::vector<std::vector<Term>> rows = rows_in;
+    std::vector<int> dst_cell(rows.size());
+    for (size_t r = 0; r < rows.size(); ++r)
+        dst_cell[r] = (int)r;
+    std::vector<int32_t> split_row, split_first(1, 0);
+    {
+        const size_t n_rows = rows.size();
+        int n_part = 0;
+        for (size_t r = 0; r < n_rows; ++r) {
+            const size_t len = rows[r].size();
+            if (len <= (size_t)kSplitAbove)
+                continue;
+            std::vector<Term> whole = std::move(rows[r]);
+            split_row.push_back((int32_t)r);
+            for (size_t b = 0; b < len; b += kSplitChunk) {
+                std::vector<Term> part(whole.begin() + b,
+                                       whole.begin() + std::min(len, b + (size_t)kSplitChunk));
+                if (b == 0) {
+                    rows[r] = std::move(part);
+                    dst_cell[r] = 2 * N + 1 + n_part;
+                } else {
+                    rows.push_back(std::move(part));
+                    dst_cell.push_back(2 * N + 1 + n_part);
+                }
+                ++n_part;
+            }
+            split_first.push_back(n_part);
+        }
+        L.n_part = n_part;
+        if (2 * N + 1 + n_part > 2047)
+            return;  // 1 | (out cell << 1) fits 12 bits
+    }
     auto padded = [&](size_t r) { return (int)std::max<size_t>(4, (rows[r].size() + 3) / 4 * 4); };
     std::vector<int> order(rows.size());
     for (size_t r = 0; r < rows.size(); ++r)
@@ -229,7 +270,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
             }
             start += padded(row);
             const int blk = start / 4 - 1;  // the row ends in this block
-            const uint32_t meta = 1u | ((uint32_t)row << 1);
+            const uint32_t meta = 1u | ((uint32_t)dst_cell[row] << 1);
             for (int e = 0; e < 4; ++e) {
                 desc[(size_t)(4 * blk + e) * lanes + l] |= (meta >> (3 * e)) & 7u;
                 desc32[(size_t)(4 * blk + e) * lanes + l] |= ((meta >> (3 * e)) & 7u) << 13;
@@ -246,6 +287,8 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     };
     const size_t o_desc = carve(desc.size() * 4), o_rx = carve(rx.size() * 4);
     const size_t o_desc32 = carve(desc32.size() * 4);
+    const size_t o_srow = carve(std::max<size_t>(1, split_row.size()) * 4);
+    const size_t o_sfirst = carve(split_first.size() * 4);
     if (hipMalloc(&L.dev, off) != hipSuccess) {
         L.dev = nullptr;
         return;
@@ -259,6 +302,9 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     put(o_desc, desc.data(), desc.size() * 4);
     put(o_rx, rx.data(), rx.size() * 4);
     put(o_desc32, desc32.data(), desc32.size() * 4);
+    if (!split_row.empty())
+        put(o_srow, split_row.data(), split_row.size() * 4);
+    put(o_sfirst, split_first.data(), split_first.size() * 4);
     if (e != hipSuccess)
         return;
     L.sn.n_species = N;
@@ -267,6 +313,9 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L.sn.end_mask = end_mask;
     L.sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc);
     L.sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
+    L.sn.n_split = (int32_t)split_row.size();
+    L.sn.split_row = reinterpret_cast<const int32_t *>(base + o_srow);
+    L.sn.split_first = reinterpret_cast<const int32_t *>(base + o_sfirst);
     L.sn32 = L.sn;
     L.sn32.desc = reinterpret_cast<const uint32_t *>(base + o_desc32);
     L.ok32 = ok32;
@@ -278,9 +327,10 @@ size_t lds_bytes_variant0(const asy_network *net)
     return sizeof(double) * ((size_t)net->n_reactions + 2 * (size_t)net->n_species);
 }
 
-size_t lds_bytes_variant1(const asy_network *net, int zones_per_group)
+size_t lds_bytes_variant1(const asy_network *net, int W, int zones_per_group)
 {
-    return sizeof(double) * (size_t)strat_zone_cells(net->n_species) * zones_per_group;
+    return sizeof(double) *
+           (size_t)strat_zone_cells(net->n_species, net->strat[w_index(W)].n_part) * zones_per_group;
 }
 
 asy_status validate_launch(const asy_network *net, const asy_launch *c)
@@ -312,7 +362,7 @@ asy_status validate_launch(const asy_network *net, const asy_launch *c)
         if (!net->strat[w_index(W)].ok)
             return fail(ASY_ENOTSUP, "variant 1 has no kernel instance for this network with " +
                                          std::to_string(c->threads_per_zone) + " threads per zone");
-        if (lds_bytes_variant1(net, c->zones_per_group) > net->lds_per_group_max)
+        if (lds_bytes_variant1(net, W, c->zones_per_group) > net->lds_per_group_max)
             return fail(ASY_ENOTSUP, "variant 1: zones do not fit the LDS of one workgroup");
         return ASY_OK;
     }
@@ -380,7 +430,7 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
         if (c.groups_per_cu > 0)
             grid = std::min(grid, c.groups_per_cu * net->n_cu);
         hipLaunchKernelGGL(inst->fn, dim3(grid), dim3(c.threads_per_zone * zpg),
-                           lds_bytes_variant1(net, zpg), s, mode == 4 ? L.sn32 : L.sn, o, za, rates,
+                           lds_bytes_variant1(net, W, zpg), s, mode == 4 ? L.sn32 : L.sn, o, za, rates,
                            order, la);
         return hipGetLastError();
     }

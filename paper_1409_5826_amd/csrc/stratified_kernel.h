@@ -37,7 +37,13 @@ struct StratNetwork {
     uint64_t end_mask;         // bit b: some lane ends a row in block b (slots 4b..4b+3)
     const uint32_t *desc;      // [C][lanes]: byte offset of Y[x] (+ 3 row-end bits) | byte
                                // offset of Y[y] << 16, in the zone's LDS block
-    const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
+    const int32_t *rx;
+    // rows longer than the lanes' average work are summed in chunks into partial cells
+    // (out[2N + 1 + p]); split row q's partials are cells split_first[q] .. split_first[q+1]-1,
+    // added in that order into out[split_row[q]]
+    int32_t n_split;
+    const int32_t *split_row;
+    const int32_t *split_first;         // [C][lanes]: reaction of the term, -1 for padding
 };
 
 // Arrhenius rates of every zone, k[z][j] = A_j exp(-E_j / T_z), once per call.
@@ -150,10 +156,10 @@ struct LearnArgs {
     int32_t trace_zones; // only zones below this index record
 };
 
-// LDS doubles one zone needs: Y[0..N] (Y[N] = 1.0) and out[0..2N] (out[2N] collects padding rows).
-__host__ __device__ inline int strat_zone_cells(int n_species)
+// LDS doubles one zone needs: Y[0..N] (Y[N] = 1.0), out[0..2N] and n_part partial sums.
+__host__ __device__ inline int strat_zone_cells(int n_species, int n_part = 0)
 {
-    const int cells = (n_species + 1) + (2 * n_species + 1);
+    const int cells = (n_species + 1) + (2 * n_species + 1) + n_part;
     return (cells + 31) / 32 * 32;  // 256-byte aligned zone blocks
 }
 
@@ -421,6 +427,18 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                     dq[s] = dsc[s * LANES];
             }
             zone_sync<W>();
+            if (sn.n_split > 0) {
+                // split rows: their chunk sums, added in chunk order
+                const T *part = out + (2 * N + 1);
+                for (int q = zl; q < sn.n_split; q += LANES) {
+                    const int f = sn.split_first[q], l = sn.split_first[q + 1];
+                    T sum = part[f];
+                    for (int c = f + 1; c < l; ++c)
+                        sum = sum + part[c];
+                    out[sn.split_row[q]] = sum;
+                }
+                zone_sync<W>();
+            }
 
             // kappa-switched update of the lane's species and the change measure
             T yn[SPL];

@@ -149,12 +149,17 @@ def make_network(
     seed: int,
     min_incidence: int = 4,
     arrhenius: Optional[tuple[float, float, float, float]] = None,
+    hubs: tuple = (),
+    hub_fraction: float = 0.0,
 ) -> Network:
     """Draw a weight-conserving random network.
 
     mass_group species share each weight: w_i = 1 + floor(i / mass_group).
     arrhenius = (log10A_lo, log10A_hi, E_lo, E_hi) draws log10 A_j ~ U(log10A_lo,
     log10A_hi) and E_j ~ U(E_lo, E_hi); None leaves rates to the zones.
+    hubs / hub_fraction: that fraction of the two-body reactions drawn after the
+    coverage phase has a hub species as a reactant (light particles captured by
+    everything, as protons, neutrons and alpha particles are in nuclear networks).
     """
     rng = _rng(seed)
     weight = (1 + np.arange(n_species) // mass_group).astype(np.int32)
@@ -210,7 +215,16 @@ def make_network(
     for idx in rng.choice(rest1, size=n_one_body - n1, replace=False):
         take1(int(idx))
     rest2 = np.flatnonzero(~used2)
-    for idx in rng.choice(rest2, size=n_two_body - n2, replace=False):
+    left2 = n_two_body - n2
+    if hubs and hub_fraction > 0.0:
+        hub = np.isin(two[:, 0], hubs) | np.isin(two[:, 1], hubs)
+        rest_hub, rest_other = rest2[hub[rest2]], rest2[~hub[rest2]]
+        n_hub = min(len(rest_hub), int(round(hub_fraction * left2)))
+        picks = np.concatenate([rng.choice(rest_hub, size=n_hub, replace=False),
+                                rng.choice(rest_other, size=left2 - n_hub, replace=False)])
+    else:
+        picks = rng.choice(rest2, size=left2, replace=False)
+    for idx in picks:
         take2(int(idx))
 
     sel1 = one[used1]
@@ -309,6 +323,18 @@ def _n150_arrh(n_zones=4096, e_window=None):
                     extra={"E_window": (e_lo, e_hi)})
 
 
+def _n150_hub(n_zones=4096, e_window=None):
+    e_lo, e_hi = ARRHENIUS_E_WINDOW_N150 if e_window is None else e_window
+    net = make_network(150, 481, 1123, mass_group=5, seed=1005, arrhenius=(2.0, 12.0, e_lo, e_hi),
+                       hubs=(0, 1, 15), hub_fraction=0.6)
+    zones = make_zones(net, n_zones, seed=2005, t_end=1.0, T_range=(1.0, 4.0))
+    return Workload("n150_r1604_hub_arrhenius", net, zones, 0.01,
+                    "150 species, 1604 reactions, 60 % of the freely drawn two-body reactions "
+                    "capture one of 3 hub species (weights 1, 1, 4), Arrhenius rates as the "
+                    "150-species workload, T log-uniform 1..4 per zone, t_end 1 s",
+                    extra={"E_window": (e_lo, e_hi), "hubs": (0, 1, 15)})
+
+
 def _n365_arrh(n_zones=1024, e_window=None):
     e_lo, e_hi = ARRHENIUS_E_WINDOW_N365 if e_window is None else e_window
     net = make_network(365, 1320, 3080, mass_group=6, seed=1004, arrhenius=(2.0, 12.0, e_lo, e_hi))
@@ -358,6 +384,7 @@ PRESETS = {
     "n150_r1604_const": _n150_const,
     "n150_r1604_arrhenius": _n150_arrh,
     "n365_r4400_arrhenius": _n365_arrh,
+    "n150_r1604_hub_arrhenius": _n150_hub,
 }
 
 

@@ -1,0 +1,105 @@
+"""GPU integration of a network with hub species (3 species in about 200 reactions each).
+
+Rows of more than 64 terms are summed in chunks of 32 consecutive terms whose partial sums are
+then added in order, so the hub rows round differently from the oracle's one-pass ascending sum
+(all terms are non-negative: the difference is a few ulps).  Bar: the parity bar of the double
+path (relative error <= 1e-9 on every species above 1e-20, accepted steps within 1 %, identical
+status).  The chunking does not depend on the launch, so all launch configurations agree bit for
+bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_5826_amd import binding, workloads
+
+pytestmark = pytest.mark.gpu
+
+NAME = "n150_r1604_hub_arrhenius"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+
+    assert torch.cuda.is_available()
+    binding.lib()
+    yield
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run(wl, launch=None, precision=0):
+    import torch
+
+    net = binding.Network(wl.network)
+    try:
+        if launch:
+            net.set_launch(**launch)
+        used = net.get_launch()
+        buf = net.zone_buffers(wl.zones)
+        net.integrate(buf, binding.options_default(precision=precision))
+        torch.cuda.synchronize()
+        out = {k: (None if v is None else v.cpu().numpy()) for k, v in buf.items()}
+        out["launch"] = used
+        return out
+    finally:
+        net.close()
+
+
+def check(g, ref, idx, rel_tol, y_min):
+    np.testing.assert_array_equal(g["zone_status"][idx], ref["status"])
+    assert (np.abs(g["n_accepted"][idx] - ref["n_acc"]) <= 0.01 * ref["n_acc"]).all()
+    big = ref["Y"] > y_min
+    rel = np.abs(g["Y"][idx] - ref["Y"])[big] / ref["Y"][big]
+    assert rel.max() <= rel_tol, f"max rel {rel.max():.3e}"
+    return rel.max()
+
+
+def test_hub_network_is_split_and_packed():
+    wl = workloads.preset(NAME, n_zones=4)
+    net = wl.network
+    kd = np.bincount(net.reactant0, minlength=150) + np.bincount(net.reactant1[net.reactant1 >= 0],
+                                                                 minlength=150)
+    assert np.sort(kd)[-3:].min() > 150  # three hub rows of ~200 terms
+    h = binding.Network(net)
+    try:
+        launch = h.get_launch()
+        # default launch: the packed kernel, not the generic fallback
+        assert launch["variant"] == 1 and launch["threads_per_zone"] == 128
+    finally:
+        h.close()
+
+
+def test_hub_parity_full_batch_sampled():
+    wl = workloads.preset(NAME)
+    say(f"case hub {NAME} zones={wl.zones.n_zones} sampled=40")
+    g = run(wl)
+    idx = np.random.default_rng(8).choice(wl.zones.n_zones, 40, replace=False)
+    ref = oracle.integrate_batch(wl.network, wl.zones.subset(idx))
+    say(f"  max rel {check(g, ref, idx, 1e-9, 1e-20):.2e}; launch {g['launch']}")
+    assert (g["zone_status"] == binding.ZONE_OK).all()
+
+
+def test_hub_launch_invariance_and_f32():
+    wl = workloads.preset(NAME, n_zones=48)
+    say("case hub launch invariance zones=48")
+    outs = [run(wl, launch=dict(variant=1, threads_per_zone=64 * W, zone_order=zo))
+            for W, zo in [(1, 1), (2, 1), (4, 0)]]
+    for o in outs[1:]:
+        for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
+            np.testing.assert_array_equal(o[key], outs[0][key])
+    # single precision: the chunked hub sums round differently in float, and a few thousand
+    # stiff steps amplify that; statuses and step counts still agree, most species to 1e-5
+    g32 = run(wl, precision=1)
+    ref32 = oracle.integrate_batch(wl.network, wl.zones, precision=1)
+    np.testing.assert_array_equal(g32["zone_status"], ref32["status"])
+    assert (np.abs(g32["n_accepted"] - ref32["n_acc"]) <= 0.01 * ref32["n_acc"]).all()
+    big = ref32["Y"] > 1e-20
+    rel = np.abs(g32["Y"] - ref32["Y"])[big] / ref32["Y"][big]
+    say(f"  f32 rel median {np.median(rel):.2e} max {rel.max():.2e}")
+    assert np.median(rel) <= 1e-5 and rel.max() <= 2e-2
