@@ -93,6 +93,11 @@ typedef struct {
     int32_t rate_form;        /* ASY_RATES_PER_ZONE or ASY_RATES_ARRHENIUS */
     const double *A;          /* [R] Arrhenius prefactors (> 0, finite); NULL for per-zone rates */
     const double *E;          /* [R] activation energies in units of T (finite); NULL for per-zone rates */
+    int32_t split_above;      /* rows (creation or depletion sums of one species) with more terms are
+                                 summed in chunks of split_above / 2 terms (rounded down to a multiple
+                                 of 4) on separate lanes, the chunk sums added in order: 0 = 64.
+                                 Splitting changes the order of the additions of such rows (results
+                                 differ by rounding, independent of the launch) */
 } asy_network_desc;
 
 /*

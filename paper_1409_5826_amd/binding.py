@@ -70,6 +70,7 @@ class asy_network_desc(C.Structure):
         ("rate_form", C.c_int32),
         ("A", C.c_void_p),
         ("E", C.c_void_p),
+        ("split_above", C.c_int32),
     ]
 
 
@@ -181,7 +182,8 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def asy_network_create(n_species, reactant0, reactant1, product, weight=None, A=None, E=None):
+def asy_network_create(n_species, reactant0, reactant1, product, weight=None, A=None, E=None,
+                       split_above=0):
     """Create a handle from host arrays; returns the opaque pointer (int)."""
     r0, r1, pr = _i32(reactant0), _i32(reactant1), _i32(product)
     w = None if weight is None else _i32(weight)
@@ -192,7 +194,8 @@ def asy_network_create(n_species, reactant0, reactant1, product, weight=None, A=
         reactant0=r0.ctypes.data, reactant1=r1.ctypes.data, product=pr.ctypes.data,
         weight=None if w is None else w.ctypes.data,
         rate_form=RATES_ARRHENIUS if (a is not None or e is not None) else RATES_PER_ZONE,
-        A=None if a is None else a.ctypes.data, E=None if e is None else e.ctypes.data)
+        A=None if a is None else a.ctypes.data, E=None if e is None else e.ctypes.data,
+        split_above=int(split_above))
     h = C.c_void_p()
     _check(lib().asy_network_create(C.byref(d), C.byref(h)), "asy_network_create")
     return h.value
@@ -343,12 +346,12 @@ def asy_version() -> str:
 class Network:
     """Convenience owner of a handle built from a workloads.Network."""
 
-    def __init__(self, net):
+    def __init__(self, net, split_above=0):
         self.n_species = int(net.n_species)
         self.n_reactions = int(net.n_reactions)
         self.arrhenius = net.A is not None
         self.handle = asy_network_create(net.n_species, net.reactant0, net.reactant1, net.product,
-                                         net.weight, net.A, net.E)
+                                         net.weight, net.A, net.E, split_above)
 
     def close(self):
         if self.handle:

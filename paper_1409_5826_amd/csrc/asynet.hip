@@ -176,23 +176,24 @@ std::vector<std::vector<Term>> network_rows(int N, int R, const int32_t *r0, con
     return rows;
 }
 
-constexpr int kSplitAbove = 64;  // rows with more terms are summed in chunks
-constexpr int kSplitChunk = 32;  // terms per chunk of a split row
+constexpr int kSplitAboveDefault = 64;  // rows with more terms are summed in chunks
 
 // Pack the rows onto 64*W lanes: every row padded to a multiple of 4 terms
 // (at least 4, so that an empty row still writes its 0.0), longest first,
 // each onto the lane with the least work so far (lowest lane on ties).
 // Leaves L.ok false when no compiled instance can hold the layout.
-void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows_in)
+void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows_in,
+                 int split_above)
 {
+    const int chunk = std::max(4, split_above / 2 / 4 * 4);  // terms per chunk of a split row
     StratLayout &L = net->strat[w_index(W)];
     L = StratLayout{};
     const int N = net->n_species;
     const int lanes = 64 * W;
     if ((N + 1) * 8 > 65528 || 2 * N > 2047)
         return;  // Y byte offsets fit 16 bits; 1 | (out cell << 1) fits 12 bits
-    // Rows of more than kSplitAbove terms (hub species: far longer than the lanes' average
-    // work) are split into chunks of kSplitChunk consecutive terms; chunk k of a split row is
+    // Rows of more than split_above terms (by default hub species: far longer than the lanes'
+    // average work) are split into chunks of `chunk` consecutive terms; chunk k of a split row is
     // a row of its own summing into partial cell 2N + 1 + p, and the kernel adds a split
     // row's partials in chunk order.  The rule does not depend on the launch, so every
     // launch configuration computes the same sums.
@@ -206,13 +207,13 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         int n_part = 0;
         for (size_t r = 0; r < n_rows; ++r) {
             const size_t len = rows[r].size();
-            if (len <= (size_t)kSplitAbove)
+            if (len <= (size_t)split_above)
                 continue;
             std::vector<Term> whole = std::move(rows[r]);
             split_row.push_back((int32_t)r);
-            for (size_t b = 0; b < len; b += kSplitChunk) {
+            for (size_t b = 0; b < len; b += chunk) {
                 std::vector<Term> part(whole.begin() + b,
-                                       whole.begin() + std::min(len, b + (size_t)kSplitChunk));
+                                       whole.begin() + std::min(len, b + (size_t)chunk));
                 if (b == 0) {
                     rows[r] = std::move(part);
                     dst_cell[r] = 2 * N + 1 + n_part;
@@ -745,6 +746,8 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     const int32_t N = d->n_species, R = d->n_reactions;
     if (N < 1 || R < 1)
         return fail(ASY_EINVAL, "n_species and n_reactions must be >= 1");
+    if (d->split_above < 0 || (d->split_above > 0 && d->split_above < 8))
+        return fail(ASY_EINVAL, "split_above must be 0 or >= 8");
     if (N > 32000 || R > (1 << 24))
         return fail(ASY_EINVAL, "network too large (n_species <= 32000, n_reactions <= 2^24)");
     if (!d->reactant0 || !d->reactant1 || !d->product)
@@ -897,8 +900,9 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     // variant 1 layouts
     {
         const auto rows = network_rows(N, R, d->reactant0, d->reactant1, d->product);
+        const int split_above = d->split_above > 0 ? d->split_above : kSplitAboveDefault;
         for (int W : {1, 2, 4})
-            build_strat(net, W, rows);
+            build_strat(net, W, rows, split_above);
     }
     // default launch: variant 1 with the least slot work per zone step (slots
     // per lane x waves), slots beyond 64 per lane weighted 1.25 for the

@@ -71,6 +71,8 @@ def test_descriptor_validation():
     assert "Arrhenius" in _expect_einval(A=np.full(R, -1.0), E=np.zeros(R))
     _expect_einval(A=np.full(R, np.nan), E=np.zeros(R))
     _expect_einval(A=np.ones(R), E=np.full(R, np.inf))
+    assert "split_above" in _expect_einval(split_above=5)
+    assert "split_above" in _expect_einval(split_above=-1)
 
 
 def test_valid_descriptor_needs_a_device():

@@ -103,3 +103,27 @@ def test_hub_launch_invariance_and_f32():
     rel = np.abs(g32["Y"] - ref32["Y"])[big] / ref32["Y"][big]
     say(f"  f32 rel median {np.median(rel):.2e} max {rel.max():.2e}")
     assert np.median(rel) <= 1e-5 and rel.max() <= 2e-2
+
+
+def test_split_threshold_option():
+    """A lower split threshold (split_above) chunks the ordinary rows too: the results stay within
+    the parity bar of the oracle and do not depend on the launch."""
+    import torch
+
+    wl = workloads.preset("n150_r1604_arrhenius", n_zones=24)
+    say("case split_above=24 n150_r1604_arrhenius zones=24")
+    outs = []
+    for W in (2, 4):
+        net = binding.Network(wl.network, split_above=24)
+        try:
+            net.set_launch(variant=1, threads_per_zone=64 * W, zone_order=1)
+            buf = net.zone_buffers(wl.zones)
+            net.integrate(buf)
+            torch.cuda.synchronize()
+            outs.append({k: (None if v is None else v.cpu().numpy()) for k, v in buf.items()})
+        finally:
+            net.close()
+    for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
+        np.testing.assert_array_equal(outs[1][key], outs[0][key])
+    ref = oracle.integrate_batch(wl.network, wl.zones)
+    say(f"  max rel {check(outs[0], ref, np.arange(24), 1e-9, 1e-20):.2e}")
