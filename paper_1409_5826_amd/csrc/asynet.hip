@@ -39,8 +39,8 @@ asy_status fail(asy_status st, const std::string &msg)
 // Layout of variant 1 for one choice of waves per zone.
 struct StratLayout {
     int W = 0, lanes = 0, C_needed = 0, C = 0, SPL = 0;
-    int n_part = 0;       // partial-sum cells of split rows
-    bool ok32 = false;    // the single-precision descriptors exist (N <= 2046)
+    int n_split = 0;      // rows summed in chunks
+    bool ok32 = false;    // the single-precision tables exist
     StratNetwork sn32{};  // the same layout with descriptors for float cells
     void *dev = nullptr;
     StratNetwork sn{};
@@ -155,6 +155,25 @@ const StratInstance *find_strat_instance(int W, int SPL, int C_needed, int mode 
 
 int w_index(int W) { return W == 1 ? 0 : (W == 2 ? 1 : 2); }
 
+// Variant 1's tables hold absolute LDS addresses, valid because its kernels
+// declare no static LDS, so their dynamic LDS starts at address 0.  Checked
+// once per process on the kernels' attributes.
+asy_status check_strat_lds_base()
+{
+    static int checked = 0;  // 0 not yet, 1 good, -1 bad
+    if (checked == 0) {
+        checked = 1;
+        for (const auto &in : kStratInstances) {
+            hipFuncAttributes a{};
+            if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(in.fn)) != hipSuccess ||
+                a.sharedSizeBytes != 0)
+                checked = -1;
+        }
+    }
+    return checked == 1 ? ASY_OK
+                        : fail(ASY_EDEVICE, "variant 1 kernels must not use static LDS");
+}
+
 // Rows of the network: row i (< N) sums the creation flux of species i, row
 // N + i its depletion rate; terms in ascending reaction index.  A term is
 // (rx, x, y) with x, y LDS cells of Y (cell N holds 1.0).
@@ -181,7 +200,9 @@ constexpr int kSplitAboveDefault = 64;  // rows with more terms are summed in ch
 // Pack the rows onto 64*W lanes: every row padded to a multiple of 4 terms
 // (at least 4, so that an empty row still writes its 0.0), longest first,
 // each onto the lane with the least work so far (lowest lane on ties).
-// Leaves L.ok false when no compiled instance can hold the layout.
+// Row sums take the cells after Y in lane order (lane 0's rows first, each
+// lane's in its slot order); split rows' totals follow.  Leaves L.ok false
+// when no compiled instance can hold the layout.
 void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows_in,
                  int split_above)
 {
@@ -190,45 +211,38 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L = StratLayout{};
     const int N = net->n_species;
     const int lanes = 64 * W;
-    if ((N + 1) * 8 > 65528 || 2 * N > 2047)
-        return;  // Y byte offsets fit 16 bits; 1 | (out cell << 1) fits 12 bits
+    if (N * 8 > 0x7fff)
+        return;  // the byte address of Y[y] fits the 15 bits below the row-end bit
     // Rows of more than split_above terms (by default hub species: far longer than the lanes'
-    // average work) are split into chunks of `chunk` consecutive terms; chunk k of a split row is
-    // a row of its own summing into partial cell 2N + 1 + p, and the kernel adds a split
-    // row's partials in chunk order.  The rule does not depend on the launch, so every
-    // launch configuration computes the same sums.
+    // average work) are split into chunks of `chunk` consecutive terms; every chunk is a row of
+    // its own, and the kernel adds a split row's chunk sums in chunk order.  The rule does not
+    // depend on the launch, so every launch configuration computes the same sums.
     std::vector<std::vector<Term>> rows = rows_in;
-    std::vector<int> dst_cell(rows.size());
-    for (size_t r = 0; r < rows.size(); ++r)
-        dst_cell[r] = (int)r;
-    std::vector<int32_t> split_row, split_first(1, 0);
+    std::vector<std::vector<int>> split_chunks;  // per split row: its packed rows, in chunk order
+    std::vector<int> split_of(rows.size(), -1);  // original row -> split index
     {
         const size_t n_rows = rows.size();
-        int n_part = 0;
         for (size_t r = 0; r < n_rows; ++r) {
             const size_t len = rows[r].size();
             if (len <= (size_t)split_above)
                 continue;
             std::vector<Term> whole = std::move(rows[r]);
-            split_row.push_back((int32_t)r);
+            split_of[r] = (int)split_chunks.size();
+            split_chunks.emplace_back();
             for (size_t b = 0; b < len; b += chunk) {
                 std::vector<Term> part(whole.begin() + b,
                                        whole.begin() + std::min(len, b + (size_t)chunk));
                 if (b == 0) {
                     rows[r] = std::move(part);
-                    dst_cell[r] = 2 * N + 1 + n_part;
+                    split_chunks.back().push_back((int)r);
                 } else {
+                    split_chunks.back().push_back((int)rows.size());
                     rows.push_back(std::move(part));
-                    dst_cell.push_back(2 * N + 1 + n_part);
                 }
-                ++n_part;
             }
-            split_first.push_back(n_part);
         }
-        L.n_part = n_part;
-        if (2 * N + 1 + n_part > 2047)
-            return;  // 1 | (out cell << 1) fits 12 bits
     }
+    const int n_split = (int)split_chunks.size();
     auto padded = [&](size_t r) { return (int)std::max<size_t>(4, (rows[r].size() + 3) / 4 * 4); };
     std::vector<int> order(rows.size());
     for (size_t r = 0; r < rows.size(); ++r)
@@ -252,43 +266,77 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         return;  // end_mask holds at most 64 blocks of 4 slots
     const int C = inst->C;
     L.C = C;
-    // descriptors hold byte offsets of the two Y cells (cell N = 1.0); padding
-    // terms read ONE twice and carry a zero rate
-    const uint32_t one = (uint32_t)N * 8u, one32 = (uint32_t)N * 4u;
-    std::vector<uint32_t> desc((size_t)C * lanes, one | (one << 16));
-    std::vector<uint32_t> desc32((size_t)C * lanes, one32 | (one32 << 16));
-    std::vector<int32_t> rx((size_t)C * lanes, -1);
-    uint64_t end_mask = 0;
-    for (int l = 0; l < lanes; ++l) {
-        int start = 0;
-        for (int row : lane_rows[l]) {
-            const auto &terms = rows[row];
-            for (size_t e = 0; e < terms.size(); ++e) {
-                const size_t at = (size_t)(start + (int)e) * lanes + l;
-                desc[at] = (uint32_t)terms[e].x * 8u | ((uint32_t)terms[e].y * 8u << 16);
-                desc32[at] = (uint32_t)terms[e].x * 4u | ((uint32_t)terms[e].y * 4u << 16);
-                rx[at] = terms[e].rx;
-            }
-            start += padded(row);
-            const int blk = start / 4 - 1;  // the row ends in this block
-            const uint32_t meta = 1u | ((uint32_t)dst_cell[row] << 1);
-            for (int e = 0; e < 4; ++e) {
-                desc[(size_t)(4 * blk + e) * lanes + l] |= (meta >> (3 * e)) & 7u;
-                desc32[(size_t)(4 * blk + e) * lanes + l] |= ((meta >> (3 * e)) & 7u) << 13;
-            }
-            end_mask |= 1ull << blk;
+    // cells: Y[0..N) and ONE (cell N), then the packed rows' sums in lane order, then the
+    // totals of split rows
+    const int n_packed = (int)rows.size();
+    std::vector<int> cell(rows.size());
+    std::vector<int> lane_first(lanes);
+    {
+        int next = N + 1;
+        for (int l = 0; l < lanes; ++l) {
+            lane_first[l] = next;
+            for (int row : lane_rows[l])
+                cell[row] = next++;
         }
     }
-    const bool ok32 = (N + 1) * 4 <= 8191;  // float byte addresses stay below bit 13
+    const int n_cells = N + 1 + n_packed + n_split;
+    if ((size_t)n_cells * 8 > 0x10000)
+        return;  // cell addresses fit 16 bits
+    auto total_cell = [&](int orig) {
+        return split_of[orig] >= 0 ? N + 1 + n_packed + split_of[orig] : cell[orig];
+    };
+    L.n_split = n_split;
+    // tables for cells of `bytes` bytes: [0] double, [1] float
+    std::vector<uint32_t> desc[2], lane_out[2], species_out[2], split_src[2];
+    std::vector<int32_t> rx((size_t)C * lanes, -1), split_first(1, 0);
+    for (const auto &ch : split_chunks)
+        split_first.push_back(split_first.back() + (int32_t)ch.size());
+    uint64_t end_mask = 0;
+    for (int p = 0; p < 2; ++p) {
+        const uint32_t B = p == 0 ? 8u : 4u;
+        // padding terms read ONE twice and carry a zero rate
+        const uint32_t one = (uint32_t)N * B;
+        desc[p].assign((size_t)C * lanes, one | (one << 16));
+        for (int l = 0; l < lanes; ++l) {
+            int start = 0;
+            for (int row : lane_rows[l]) {
+                const auto &terms = rows[row];
+                for (size_t e = 0; e < terms.size(); ++e) {
+                    const size_t at = (size_t)(start + (int)e) * lanes + l;
+                    desc[p][at] = (uint32_t)terms[e].x * B | ((uint32_t)terms[e].y * B << 16);
+                    if (p == 0)
+                        rx[at] = terms[e].rx;
+                }
+                start += padded(row);
+                const int blk = start / 4 - 1;  // the row ends in this block
+                desc[p][(size_t)(4 * blk) * lanes + l] |= 0x80000000u;
+                end_mask |= 1ull << blk;
+            }
+            lane_out[p].push_back((uint32_t)lane_first[l] * B);
+        }
+        for (int i = 0; i < N; ++i)
+            species_out[p].push_back((uint32_t)total_cell(i) * B |
+                                     ((uint32_t)total_cell(N + i) * B << 16));
+        for (int q = 0; q < n_split; ++q)
+            for (int r : split_chunks[q])
+                split_src[p].push_back((uint32_t)cell[r] * B);
+        if (n_split == 0)
+            split_src[p].push_back(0);
+    }
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
         off += (bytes + 255) / 256 * 256;
         return o;
     };
-    const size_t o_desc = carve(desc.size() * 4), o_rx = carve(rx.size() * 4);
-    const size_t o_desc32 = carve(desc32.size() * 4);
-    const size_t o_srow = carve(std::max<size_t>(1, split_row.size()) * 4);
+    size_t o_desc[2], o_lane[2], o_spec[2], o_ssrc[2];
+    for (int p = 0; p < 2; ++p) {
+        o_desc[p] = carve(desc[p].size() * 4);
+        o_lane[p] = carve(lane_out[p].size() * 4);
+        o_spec[p] = carve(species_out[p].size() * 4);
+        o_ssrc[p] = carve(split_src[p].size() * 4);
+    }
+    const size_t o_rx = carve(rx.size() * 4);
     const size_t o_sfirst = carve(split_first.size() * 4);
     if (hipMalloc(&L.dev, off) != hipSuccess) {
         L.dev = nullptr;
@@ -300,26 +348,37 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         if (e == hipSuccess)
             e = hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
     };
-    put(o_desc, desc.data(), desc.size() * 4);
+    for (int p = 0; p < 2; ++p) {
+        put(o_desc[p], desc[p].data(), desc[p].size() * 4);
+        put(o_lane[p], lane_out[p].data(), lane_out[p].size() * 4);
+        put(o_spec[p], species_out[p].data(), species_out[p].size() * 4);
+        put(o_ssrc[p], split_src[p].data(), split_src[p].size() * 4);
+    }
     put(o_rx, rx.data(), rx.size() * 4);
-    put(o_desc32, desc32.data(), desc32.size() * 4);
-    if (!split_row.empty())
-        put(o_srow, split_row.data(), split_row.size() * 4);
     put(o_sfirst, split_first.data(), split_first.size() * 4);
     if (e != hipSuccess)
         return;
-    L.sn.n_species = N;
-    L.sn.n_reactions = net->n_reactions;
-    L.sn.n_slots = C_needed;
-    L.sn.end_mask = end_mask;
-    L.sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc);
-    L.sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
-    L.sn.n_split = (int32_t)split_row.size();
-    L.sn.split_row = reinterpret_cast<const int32_t *>(base + o_srow);
-    L.sn.split_first = reinterpret_cast<const int32_t *>(base + o_sfirst);
-    L.sn32 = L.sn;
-    L.sn32.desc = reinterpret_cast<const uint32_t *>(base + o_desc32);
-    L.ok32 = ok32;
+    for (int p = 0; p < 2; ++p) {
+        StratNetwork &sn = p == 0 ? L.sn : L.sn32;
+        const int B = p == 0 ? 8 : 4;
+        sn.n_species = N;
+        sn.n_reactions = net->n_reactions;
+        sn.n_slots = C_needed;
+        sn.xch = (n_cells * B + 255) / 256 * 256;
+        sn.tab = sn.xch + kStratXchBytes;
+        sn.feat = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
+        sn.end_mask = end_mask;
+        sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc[p]);
+        sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
+        sn.lane_out = reinterpret_cast<const uint32_t *>(base + o_lane[p]);
+        sn.species_out = reinterpret_cast<const uint32_t *>(base + o_spec[p]);
+        sn.n_split = n_split;
+        sn.n_chunks = split_first.back();
+        sn.split_dst = (uint32_t)(N + 1 + n_packed) * B;
+        sn.split_first = reinterpret_cast<const int32_t *>(base + o_sfirst);
+        sn.split_src = reinterpret_cast<const uint32_t *>(base + o_ssrc[p]);
+    }
+    L.ok32 = true;
     L.ok = true;
 }
 
@@ -328,10 +387,13 @@ size_t lds_bytes_variant0(const asy_network *net)
     return sizeof(double) * ((size_t)net->n_reactions + 2 * (size_t)net->n_species);
 }
 
-size_t lds_bytes_variant1(const asy_network *net, int W, int zones_per_group)
+// LDS of one workgroup of variant 1: mode 4 (single precision) has float cells;
+// modes 1-3 (traces, learned controller) add the network's input and hidden layers.
+size_t lds_bytes_variant1(const asy_network *net, int W, int mode)
 {
-    return sizeof(double) *
-           (size_t)strat_zone_cells(net->n_species, net->strat[w_index(W)].n_part) * zones_per_group;
+    const StratLayout &L = net->strat[w_index(W)];
+    const bool features = mode >= 1 && mode <= 3;
+    return strat_lds_bytes(mode == 4 ? L.sn32.feat : L.sn.feat, features);
 }
 
 asy_status validate_launch(const asy_network *net, const asy_launch *c)
@@ -363,7 +425,7 @@ asy_status validate_launch(const asy_network *net, const asy_launch *c)
         if (!net->strat[w_index(W)].ok)
             return fail(ASY_ENOTSUP, "variant 1 has no kernel instance for this network with " +
                                          std::to_string(c->threads_per_zone) + " threads per zone");
-        if (lds_bytes_variant1(net, W, c->zones_per_group) > net->lds_per_group_max)
+        if (lds_bytes_variant1(net, W, 1) > net->lds_per_group_max)
             return fail(ASY_ENOTSUP, "variant 1: zones do not fit the LDS of one workgroup");
         return ASY_OK;
     }
@@ -431,7 +493,7 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
         if (c.groups_per_cu > 0)
             grid = std::min(grid, c.groups_per_cu * net->n_cu);
         hipLaunchKernelGGL(inst->fn, dim3(grid), dim3(c.threads_per_zone * zpg),
-                           lds_bytes_variant1(net, W, zpg), s, mode == 4 ? L.sn32 : L.sn, o, za, rates,
+                           lds_bytes_variant1(net, W, mode), s, mode == 4 ? L.sn32 : L.sn, o, za, rates,
                            order, la);
         return hipGetLastError();
     }
@@ -828,6 +890,9 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(ASY_EDEVICE, std::string("device is ") + prop.gcnArchName +
                                      "; this library is built for gfx950 only");
+
+    if (check_strat_lds_base() != ASY_OK)
+        return ASY_EDEVICE;
 
     auto *net = new asy_network();
     net->n_species = N;

@@ -15,14 +15,21 @@
 // lanes of a zone's workgroup, longest first, each onto the lane with the
 // least work so far.  A lane's column is the concatenation of its rows, so a
 // row ends at the end of a block of 4 slots, at a different block on each
-// lane.  The lane learns where from its own descriptors: the low 3 bits of
-// the four descriptors of a block carry 12 bits, 1 | (out cell << 1) when the
-// lane's row ends in that block and 0 otherwise; a uniform mask (end_mask,
-// bit b: some lane ends a row in block b) skips the test in the other blocks.
+// lane.  The sums land in the LDS cells after Y in lane order -- lane l's k-th
+// row in cell lane_out[l] + k -- so a lane needs only one bit per block, set
+// in the first descriptor of the block where one of its rows ends, and a
+// running cell address; a uniform mask (end_mask, bit b: some lane ends a row
+// in block b) skips the test in the other blocks.  Each species' update reads
+// its two sums through a per-species pair of cell addresses.
 // The zone's rates are loaded once into registers (slot s of the lane holds
 // the rate of its term s), so per step the only random LDS traffic is the
 // abundance gathers.  The term descriptors stream from global memory in
 // slot-major order and stay in the L1/L2 caches for all zones.
+//
+// The kernel keeps all of its LDS in the dynamic allocation (it declares no
+// static LDS), which therefore starts at LDS address 0: descriptors and cell
+// tables hold absolute LDS byte addresses, and a gather is one mask or
+// bit-field extract of a descriptor.
 #pragma once
 
 #include "integrate_kernels.h"
@@ -34,17 +41,48 @@ struct StratNetwork {
     int32_t n_species;
     int32_t n_reactions;
     int32_t n_slots;           // slots used (<= compile-time C)
+    int32_t xch;               // LDS byte address of the exchange area (after the zone's cells)
+    int32_t tab;               // LDS byte address of species_out (lane-major: species
+                               // zl + m * lanes at zl * SPL + m), split_first and split_src
+    int32_t feat;              // LDS byte address of the learned controller's input and layers
     uint64_t end_mask;         // bit b: some lane ends a row in block b (slots 4b..4b+3)
-    const uint32_t *desc;      // [C][lanes]: byte offset of Y[x] (+ 3 row-end bits) | byte
-                               // offset of Y[y] << 16, in the zone's LDS block
-    const int32_t *rx;
-    // rows longer than the lanes' average work are summed in chunks into partial cells
-    // (out[2N + 1 + p]); split row q's partials are cells split_first[q] .. split_first[q+1]-1,
-    // added in that order into out[split_row[q]]
+    const uint32_t *desc;      // [C][lanes]: LDS byte address of Y[x] | that of Y[y] << 16,
+                               // bit 31 set in slot 4b when the lane ends a row in block b
+    const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
+    const uint32_t *lane_out;  // [lanes]: LDS byte address of the lane's first row sum
+    const uint32_t *species_out;  // [N]: address of F+_i | address of k_i << 16
+    // rows longer than a chunk are summed in chunks; split row q adds the sums at
+    // split_src[split_first[q] .. split_first[q+1]-1], in that order, into the cell at
+    // split_dst + q * sizeof(cell)
     int32_t n_split;
-    const int32_t *split_row;
-    const int32_t *split_first;         // [C][lanes]: reaction of the term, -1 for padding
+    int32_t n_chunks;
+    uint32_t split_dst;
+    const int32_t *split_first;   // [n_split + 1]
+    const uint32_t *split_src;    // [n_chunks]
 };
+
+// LDS of a zone's workgroup after its cells: the exchange area (cross-wave
+// reductions, the zone ticket), copies of the cell tables, and (learned
+// controller and traces) the network input and hidden layers.
+constexpr int kStratXchBytes = 128;
+constexpr int kStratFeatBytes = (kMlpInPad + 2 * kMlpHid) * 4;
+
+__host__ __device__ inline size_t strat_lds_bytes(int feat, bool features)
+{
+    return (size_t)feat + (features ? kStratFeatBytes : 0);
+}
+
+// Loads and stores at absolute LDS byte addresses.
+template <typename T>
+__device__ inline T lds_ld(uint32_t a)
+{
+    return *reinterpret_cast<const __attribute__((address_space(3))) T *>((size_t)a);
+}
+template <typename T>
+__device__ inline void lds_st(uint32_t a, T v)
+{
+    *reinterpret_cast<__attribute__((address_space(3))) T *>((size_t)a) = v;
+}
 
 // Arrhenius rates of every zone, k[z][j] = A_j exp(-E_j / T_z), once per call.
 // A non-finite T gives NaN rates and T <= 0 gives -1, which the integrator's
@@ -156,13 +194,6 @@ struct LearnArgs {
     int32_t trace_zones; // only zones below this index record
 };
 
-// LDS doubles one zone needs: Y[0..N] (Y[N] = 1.0), out[0..2N] and n_part partial sums.
-__host__ __device__ inline int strat_zone_cells(int n_species, int n_part = 0)
-{
-    const int cells = (n_species + 1) + (2 * n_species + 1) + n_part;
-    return (cells + 31) / 32 * 32;  // 256-byte aligned zone blocks
-}
-
 template <int W>
 __device__ inline void zone_sync()
 {
@@ -176,23 +207,6 @@ __device__ inline void zone_sync()
         __syncthreads();
     }
 }
-
-// Element type of the zone's cells.  A descriptor's low half is the LDS byte
-// address of Y[x] plus 3 of the 12 row-end bits of its block: in the low 3
-// bits for double cells (byte addresses are multiples of 8), in bits 13..15
-// for float cells (byte addresses are multiples of 4 and below 8192).
-template <typename T>
-struct CellCode;
-template <>
-struct CellCode<double> {
-    static constexpr uint32_t kAddr = 0xfff8u;
-    __device__ static uint32_t bits(uint32_t d) { return d & 7u; }
-};
-template <>
-struct CellCode<float> {
-    static constexpr uint32_t kAddr = 0x1fffu;
-    __device__ static uint32_t bits(uint32_t d) { return (d >> 13) & 7u; }
-};
 
 // A workgroup of W waves integrates one zone at a time.
 // Waves per SIMD (the register budget the compiler gets): the zone's rates
@@ -231,16 +245,10 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
 {
     constexpr bool FEATURES = LEARNED || TRACE;
     static_assert(!FEATURES || sizeof(T) == 8, "learned controller and trace in double only");
-    __shared__ float feat[FEATURES ? kMlpInPad : 1];
-    __shared__ float hs[FEATURES ? 2 * kMlpHid : 1];
-    __shared__ double xw_sum[W];
-    __shared__ float xw_o;
     static_assert(C % 4 == 0, "slots come in blocks of 4");
+    static_assert(W <= 4, "the exchange area holds 4 waves");
     constexpr int LANES = 64 * W;
     extern __shared__ double lds[];
-    __shared__ double xw_r[W];
-    __shared__ int xw_flag[W];
-    __shared__ int xw_zone;
 
     const int N = sn.n_species;
     const int R = sn.n_reactions;
@@ -249,7 +257,32 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     const int lane = tid % kWave;
     const int zl = tid;  // lane within the zone
     T *Y = reinterpret_cast<T *>(lds);
-    T *out = Y + (N + 1);
+    char *xb = reinterpret_cast<char *>(lds) + sn.xch;
+    double *xw_r = reinterpret_cast<double *>(xb);        // [W]
+    double *xw_sum = reinterpret_cast<double *>(xb + 32); // [W]
+    int *xw_flag = reinterpret_cast<int *>(xb + 64);      // [W]
+    int &xw_zone = *reinterpret_cast<int *>(xb + 80);
+    float &xw_o = *reinterpret_cast<float *>(xb + 84);
+    float *feat = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + sn.feat);
+    float *hs = feat + kMlpInPad;  // [2 * kMlpHid]
+    // the lane's first row-sum cell; its species' F+ / k cells, read from LDS where
+    // needed (held in registers across the step loop they would spill), lane-major
+    // so that one read fetches all of a lane's entries
+    const uint32_t wbase = sn.lane_out[zl];
+    uint32_t *tab_species = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(lds) + sn.tab);
+    int32_t *tab_first = reinterpret_cast<int32_t *>(tab_species + SPL * LANES);
+    uint32_t *tab_src = reinterpret_cast<uint32_t *>(tab_first + sn.n_split + 1);
+#pragma unroll
+    for (int m = 0; m < SPL; ++m) {
+        const int i = zl + m * LANES;
+        tab_species[zl * SPL + m] = i < N ? sn.species_out[i] : 0u;
+    }
+    if (sn.n_split > 0) {
+        for (int q = zl; q <= sn.n_split; q += LANES)
+            tab_first[q] = sn.split_first[q];
+        for (int c = zl; c < sn.n_chunks; c += LANES)
+            tab_src[c] = sn.split_src[c];
+    }
 
     for (;;) {
         // ---- next zone: a wave-wide atomic, lane 0's ticket broadcast by a cross-lane read
@@ -352,7 +385,6 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         constexpr int NB = C / 4;
         constexpr int kDescAhead = 4;    // descriptor prefetch distance, in blocks of 4 slots
         constexpr int kGatherAhead = GA; // abundance-gather distance, in blocks
-        const char *Yb = reinterpret_cast<const char *>(Y);
         uint32_t dq[C];
         const uint32_t *dsc;
         {
@@ -380,7 +412,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             // Creation fluxes and depletion rates: the lane's packed rows.
             // Rows end on multiples of 4 slots; blocks where some lane ends a
             // row are flagged in end_mask, a uniform kernel argument, so the
-            // row-end test is a scalar bit test on a compile-time block index.
+            // test is a scalar bit test on a compile-time block index, and in
+            // a flagged block the lane's own test is the sign of a descriptor.
             // Software pipeline: while block b is summed, the gathers of blocks
             // up to b+kGatherAhead and the descriptors of block b+kDescAhead are
             // in flight; the first kDescAhead blocks' descriptors of a step are
@@ -389,10 +422,11 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                 T gx[C], gy[C];
 #pragma unroll
                 for (int s = 0; s < 4 * kGatherAhead && s < C; ++s) {
-                    gx[s] = *reinterpret_cast<const T *>(Yb + (dq[s] & CellCode<T>::kAddr));
-                    gy[s] = *reinterpret_cast<const T *>(Yb + (dq[s] >> 16));
+                    gx[s] = lds_ld<T>(dq[s] & 0xffffu);
+                    gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
                 }
                 T acc = (T)0.0;
+                uint32_t wp = wbase;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -400,20 +434,18 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         dq[s] = dsc[s * LANES];
 #pragma unroll
                     for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s) {
-                        gx[s] = *reinterpret_cast<const T *>(Yb + (dq[s] & CellCode<T>::kAddr));
-                        gy[s] = *reinterpret_cast<const T *>(Yb + (dq[s] >> 16));
+                        gx[s] = lds_ld<T>(dq[s] & 0xffffu);
+                        gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
                     }
 #pragma unroll
                     for (int s = 4 * b; s < 4 * b + 4; ++s)
                         acc = acc + (kr[s] * gx[s]) * gy[s];
                     if ((emask >> b) & 1u) {
-                        using Code = CellCode<T>;
-                        const uint32_t meta = Code::bits(dq[4 * b]) | (Code::bits(dq[4 * b + 1]) << 3) |
-                                              (Code::bits(dq[4 * b + 2]) << 6) |
-                                              (Code::bits(dq[4 * b + 3]) << 9);
-                        if (meta & 1u)
-                            out[meta >> 1] = acc;
-                        acc = (meta & 1u) ? (T)0.0 : acc;
+                        if ((int32_t)dq[4 * b] < 0) {
+                            lds_st<T>(wp, acc);
+                            wp += sizeof(T);
+                            acc = (T)0.0;
+                        }
                     }
                 }
             }
@@ -429,13 +461,21 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             zone_sync<W>();
             if (sn.n_split > 0) {
                 // split rows: their chunk sums, added in chunk order
-                const T *part = out + (2 * N + 1);
                 for (int q = zl; q < sn.n_split; q += LANES) {
-                    const int f = sn.split_first[q], l = sn.split_first[q + 1];
-                    T sum = part[f];
-                    for (int c = f + 1; c < l; ++c)
-                        sum = sum + part[c];
-                    out[sn.split_row[q]] = sum;
+                    const int f = tab_first[q], l = tab_first[q + 1];
+                    T sum = lds_ld<T>(tab_src[f]);
+                    int c = f + 1;
+                    for (; c + 4 <= l; c += 4) {  // four loads in flight, added in order
+                        const T v0 = lds_ld<T>(tab_src[c]), v1 = lds_ld<T>(tab_src[c + 1]);
+                        const T v2 = lds_ld<T>(tab_src[c + 2]), v3 = lds_ld<T>(tab_src[c + 3]);
+                        sum = sum + v0;
+                        sum = sum + v1;
+                        sum = sum + v2;
+                        sum = sum + v3;
+                    }
+                    for (; c < l; ++c)
+                        sum = sum + lds_ld<T>(tab_src[c]);
+                    lds_st<T>(sn.split_dst + (uint32_t)(q * sizeof(T)), sum);
                 }
                 zone_sync<W>();
             }
@@ -445,13 +485,26 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             T rloc = (T)0.0;
             bool bad = false;
             const T hT = (T)h, kappaT = (T)o.kappa, floorT = (T)o.y_floor;
+            // the lane's sums, read together (entries past N read Y[0] and go unused)
+            T fpv[SPL], kdv[SPL];
+            {
+                uint32_t spv[SPL];
+#pragma unroll
+                for (int m = 0; m < SPL; ++m)
+                    spv[m] = tab_species[zl * SPL + m];
+#pragma unroll
+                for (int m = 0; m < SPL; ++m) {
+                    fpv[m] = lds_ld<T>(spv[m] & 0xffffu);
+                    kdv[m] = lds_ld<T>(spv[m] >> 16);
+                }
+            }
 #pragma unroll
             for (int m = 0; m < SPL; ++m) {
                 const int i = zl + m * LANES;
                 yn[m] = (T)0.0;
                 if (i < N) {
-                    const T fp = out[i];
-                    const T kd = out[N + i];
+                    const T fp = fpv[m];
+                    const T kd = kdv[m];
                     const T y = Y[i];
                     const T kh = kd * hT;
                     T v;
@@ -510,7 +563,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                             if (i < N) {
                                 const double y = yn[m];
                                 feat[i] = (float)(fmax(log10(fmax(y, 1e-300)), -30.0) / 30.0);
-                                const double kh = out[N + i] * h;
+                                const double kh = lds_ld<double>(tab_species[zl * SPL + m] >> 16) * h;
                                 kmax = fmax(kmax, kh);
                                 ksum += kh;
                             }
