@@ -12,6 +12,7 @@
 
 #include "asynet.h"
 #include "integrate_kernels.h"
+#include "lds_layout.h"
 #include "lds_probe.h"
 #include "mlp_kernels.h"
 #include "stratified_kernel.h"
@@ -40,6 +41,7 @@ asy_status fail(asy_status st, const std::string &msg)
 struct StratLayout {
     int W = 0, lanes = 0, C_needed = 0, C = 0, SPL = 0;
     int n_split = 0;      // rows summed in chunks
+    int64_t gather_cycles_before = 0, gather_cycles_after = 0;  // modelled, per zone-step
     bool ok32 = false;    // the single-precision tables exist
     StratNetwork sn32{};  // the same layout with descriptors for float cells
     void *dev = nullptr;
@@ -196,6 +198,7 @@ std::vector<std::vector<Term>> network_rows(int N, int R, const int32_t *r0, con
 }
 
 constexpr int kSplitAboveDefault = 64;  // rows with more terms are summed in chunks
+constexpr int64_t kLayoutIters = 100000;  // annealing moves per layout (~0.4 s for 150 species)
 
 // Pack the rows onto 64*W lanes: every row padded to a multiple of 4 terms
 // (at least 4, so that an empty row still writes its 0.0), longest first,
@@ -266,8 +269,35 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         return;  // end_mask holds at most 64 blocks of 4 slots
     const int C = inst->C;
     L.C = C;
-    // cells: Y[0..N) and ONE (cell N), then the packed rows' sums in lane order, then the
-    // totals of split rows
+    // bank-aware placement: which Y cell holds which species, which physical lane holds
+    // which column, the order of rows within a column
+    std::vector<int> cell_of(N + 1);
+    {
+        LayoutProblem lp;
+        lp.n_species = N;
+        lp.lanes = lanes;
+        lp.slots = C;
+        lp.rows.resize(rows.size());
+        lp.padded.resize(rows.size());
+        for (size_t r = 0; r < rows.size(); ++r) {
+            for (const Term &t : rows[r])
+                lp.rows[r].push_back({t.x, t.y});
+            lp.padded[r] = padded(r);
+        }
+        lp.lane_rows = lane_rows;
+        const LayoutResult lr = optimise_gather_layout(lp, kLayoutIters, 0x5eed0001ull + W);
+        lane_rows = lr.lane_rows;
+        for (int i = 0; i < N; ++i)
+            cell_of[i] = lr.cell_of_species[i];
+        cell_of[N] = N;
+        L.gather_cycles_before = lr.cycles_before;
+        L.gather_cycles_after = lr.cycles_after;
+    }
+    std::vector<int32_t> cell_species(N);
+    for (int i = 0; i < N; ++i)
+        cell_species[cell_of[i]] = i;
+    // cells: Y (species i in cell cell_of[i], ONE in cell N), then the packed rows' sums in
+    // lane order, then the totals of split rows
     const int n_packed = (int)rows.size();
     std::vector<int> cell(rows.size());
     std::vector<int> lane_first(lanes);
@@ -303,7 +333,8 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
                 const auto &terms = rows[row];
                 for (size_t e = 0; e < terms.size(); ++e) {
                     const size_t at = (size_t)(start + (int)e) * lanes + l;
-                    desc[p][at] = (uint32_t)terms[e].x * B | ((uint32_t)terms[e].y * B << 16);
+                    desc[p][at] = (uint32_t)cell_of[terms[e].x] * B |
+                                  ((uint32_t)cell_of[terms[e].y] * B << 16);
                     if (p == 0)
                         rx[at] = terms[e].rx;
                 }
@@ -314,9 +345,11 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
             }
             lane_out[p].push_back((uint32_t)lane_first[l] * B);
         }
-        for (int i = 0; i < N; ++i)
+        for (int c = 0; c < N; ++c) {  // by Y cell
+            const int i = cell_species[c];
             species_out[p].push_back((uint32_t)total_cell(i) * B |
                                      ((uint32_t)total_cell(N + i) * B << 16));
+        }
         for (int q = 0; q < n_split; ++q)
             for (int r : split_chunks[q])
                 split_src[p].push_back((uint32_t)cell[r] * B);
@@ -337,6 +370,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         o_ssrc[p] = carve(split_src[p].size() * 4);
     }
     const size_t o_rx = carve(rx.size() * 4);
+    const size_t o_cspec = carve(cell_species.size() * 4);
     const size_t o_sfirst = carve(split_first.size() * 4);
     if (hipMalloc(&L.dev, off) != hipSuccess) {
         L.dev = nullptr;
@@ -355,6 +389,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         put(o_ssrc[p], split_src[p].data(), split_src[p].size() * 4);
     }
     put(o_rx, rx.data(), rx.size() * 4);
+    put(o_cspec, cell_species.data(), cell_species.size() * 4);
     put(o_sfirst, split_first.data(), split_first.size() * 4);
     if (e != hipSuccess)
         return;
@@ -370,6 +405,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         sn.end_mask = end_mask;
         sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc[p]);
         sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
+        sn.cell_species = reinterpret_cast<const int32_t *>(base + o_cspec);
         sn.lane_out = reinterpret_cast<const uint32_t *>(base + o_lane[p]);
         sn.species_out = reinterpret_cast<const uint32_t *>(base + o_spec[p]);
         sn.n_split = n_split;

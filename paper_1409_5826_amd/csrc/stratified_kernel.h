@@ -29,7 +29,10 @@
 // The kernel keeps all of its LDS in the dynamic allocation (it declares no
 // static LDS), which therefore starts at LDS address 0: descriptors and cell
 // tables hold absolute LDS byte addresses, and a gather is one mask or
-// bit-field extract of a descriptor.
+// bit-field extract of a descriptor.  Which Y cell holds which species, which
+// lane holds which column and the order of rows within a column are chosen on
+// the host to spread each gather over the LDS banks (lds_layout.h); a lane
+// updates the species in its Y cells, whatever they are.
 #pragma once
 
 #include "integrate_kernels.h"
@@ -50,7 +53,8 @@ struct StratNetwork {
                                // bit 31 set in slot 4b when the lane ends a row in block b
     const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
     const uint32_t *lane_out;  // [lanes]: LDS byte address of the lane's first row sum
-    const uint32_t *species_out;  // [N]: address of F+_i | address of k_i << 16
+    const int32_t *cell_species;  // [N]: species held by Y cell c (cell N holds 1.0)
+    const uint32_t *species_out;  // [N]: by Y cell c, address of F+ | address of k << 16
     // rows longer than a chunk are summed in chunks; split row q adds the sums at
     // split_src[split_first[q] .. split_first[q+1]-1], in that order, into the cell at
     // split_dst + q * sizeof(cell)
@@ -332,9 +336,9 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         const double *Yz = za.Y + (size_t)z * N;
 #pragma unroll
         for (int m = 0; m < SPL; ++m) {
-            const int i = zl + m * LANES;
+            const int i = zl + m * LANES;  // Y cell
             if (i < N) {
-                const double y = Yz[i];
+                const double y = Yz[sn.cell_species[i]];
                 Y[i] = (T)y;
                 if (!isfinite(y))
                     flag |= 1;
@@ -562,7 +566,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                             const int i = zl + m * LANES;
                             if (i < N) {
                                 const double y = yn[m];
-                                feat[i] = (float)(fmax(log10(fmax(y, 1e-300)), -30.0) / 30.0);
+                                feat[sn.cell_species[i]] =
+                                    (float)(fmax(log10(fmax(y, 1e-300)), -30.0) / 30.0);
                                 const double kh = lds_ld<double>(tab_species[zl * SPL + m] >> 16) * h;
                                 kmax = fmax(kmax, kh);
                                 ksum += kh;
@@ -661,7 +666,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         for (int m = 0; m < SPL; ++m) {
             const int i = zl + m * LANES;
             if (i < N)
-                Yo[i] = (double)Y[i];
+                Yo[sn.cell_species[i]] = (double)Y[i];
         }
         if (zl == 0) {
             za.dt[z] = step;
