@@ -42,6 +42,7 @@ struct StratLayout {
     int W = 0, lanes = 0, C_needed = 0, C = 0, SPL = 0;
     int n_split = 0;      // rows summed in chunks
     int64_t gather_cycles_before = 0, gather_cycles_after = 0;  // modelled, per zone-step
+    uint32_t one_waves = 0;  // waves whose terms all have 1.0 as second factor
     bool ok32 = false;    // the single-precision tables exist
     StratNetwork sn32{};  // the same layout with descriptors for float cells
     void *dev = nullptr;
@@ -269,6 +270,70 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         return;  // end_mask holds at most 64 blocks of 4 slots
     const int C = inst->C;
     L.C = C;
+    // Rows whose second factors are all the 1.0 cell (depletion rows, creation rows of
+    // one-body reactions only) need no second gather and no multiply by 1.0 (exact).  A wave
+    // whose lanes hold only such rows runs a slot phase without either, so pack the other
+    // rows onto as few lanes as a cap allows (first fit, longest first: they fill the first
+    // waves), then the rest by least load, within the same C.  Keep the smallest cap that
+    // frees the most waves; with none freed, keep the plain packing.
+    std::vector<char> one_factor(rows.size());
+    for (size_t r = 0; r < rows.size(); ++r)
+        one_factor[r] = std::all_of(rows[r].begin(), rows[r].end(),
+                                    [&](const Term &t) { return t.y == N; });
+    std::vector<int> lane_start(lanes, 0);  // first slot of the lane's rows (padding before)
+    {
+        std::vector<int> other, ones;
+        for (int r : order)
+            (one_factor[r] ? ones : other).push_back(r);
+        int best_free = 0;
+        std::vector<std::vector<int>> best_rows;
+        std::vector<int> best_load;
+        const int cap0 = other.empty() ? 4 : padded(other.front());
+        for (int cap = cap0; cap <= C && best_free < W; cap += 4) {
+            std::vector<int> tload(lanes, 0);
+            std::vector<std::vector<int>> lr(lanes), lone(lanes);
+            bool ok = true;
+            int used = 0;  // lanes holding other rows: 0 .. used-1
+            for (int r : other) {
+                int l = 0;
+                while (l < lanes && tload[l] + padded(r) > cap)
+                    ++l;
+                if (l == lanes) {
+                    ok = false;
+                    break;
+                }
+                tload[l] += padded(r);
+                lr[l].push_back(r);
+                used = std::max(used, l + 1);
+            }
+            const int free_waves = ok ? W - (used + 63) / 64 : 0;
+            if (free_waves <= best_free)
+                continue;
+            for (int r : ones) {
+                const int l = (int)(std::min_element(tload.begin(), tload.end()) - tload.begin());
+                if (tload[l] + padded(r) > C) {
+                    ok = false;
+                    break;
+                }
+                tload[l] += padded(r);
+                lone[l].push_back(r);
+            }
+            if (!ok)
+                continue;
+            best_free = free_waves;
+            best_rows.assign(lanes, {});
+            for (int l = 0; l < lanes; ++l) {
+                best_rows[l] = lone[l];
+                best_rows[l].insert(best_rows[l].end(), lr[l].begin(), lr[l].end());
+            }
+            best_load = tload;
+        }
+        if (best_free > 0) {
+            lane_rows = best_rows;
+            for (int l = 0; l < lanes; ++l)
+                lane_start[l] = C - best_load[l];
+        }
+    }
     // bank-aware placement: which Y cell holds which species, which physical lane holds
     // which column, the order of rows within a column
     std::vector<int> cell_of(N + 1);
@@ -285,8 +350,11 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
             lp.padded[r] = padded(r);
         }
         lp.lane_rows = lane_rows;
+        lp.lane_start = lane_start;
+        lp.row_class.assign(rows.size(), 0);
         const LayoutResult lr = optimise_gather_layout(lp, kLayoutIters, 0x5eed0001ull + W);
         lane_rows = lr.lane_rows;
+        lane_start = lr.lane_start;
         for (int i = 0; i < N; ++i)
             cell_of[i] = lr.cell_of_species[i];
         cell_of[N] = N;
@@ -328,7 +396,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         const uint32_t one = (uint32_t)N * B;
         desc[p].assign((size_t)C * lanes, one | (one << 16));
         for (int l = 0; l < lanes; ++l) {
-            int start = 0;
+            int start = lane_start[l];
             for (int row : lane_rows[l]) {
                 const auto &terms = rows[row];
                 for (size_t e = 0; e < terms.size(); ++e) {
@@ -356,6 +424,17 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         if (n_split == 0)
             split_src[p].push_back(0);
     }
+    // bit w: every term of wave w has the 1.0 cell as second factor
+    uint32_t one_waves = 0;
+    for (int w = 0; w < W; ++w) {
+        bool all = true;
+        for (int s = 0; s < C && all; ++s)
+            for (int l = 64 * w; l < 64 * w + 64 && all; ++l)
+                all = ((desc[0][(size_t)s * lanes + l] >> 16) & 0x7fffu) == (uint32_t)N * 8u;
+        if (all)
+            one_waves |= 1u << w;
+    }
+    L.one_waves = one_waves;
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
@@ -403,6 +482,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         sn.tab = sn.xch + kStratXchBytes;
         sn.feat = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
         sn.end_mask = end_mask;
+        sn.one_waves = one_waves;
         sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc[p]);
         sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
         sn.cell_species = reinterpret_cast<const int32_t *>(base + o_cspec);

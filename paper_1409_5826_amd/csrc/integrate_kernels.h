@@ -101,6 +101,44 @@ __device__ inline double wave_max_dpp(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Maximum of non-negative values (the change measure, depletion rates): lanes
+// without a DPP source read 0, harmless for the maximum, and every row takes
+// part in the row broadcasts, so no lane keeps an old value and the moves need
+// no copies.
+#define ASY_DPP_MAX0_STEP(v, ctrl)                                                              \
+    do {                                                                                       \
+        const int lo_ = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xf, 0xf, true);     \
+        const int hi_ = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xf, 0xf, true);     \
+        v = fmax(v, __hiloint2double(hi_, lo_));                                               \
+    } while (0)
+
+__device__ inline double wave_max_nonneg_dpp(double v)
+{
+    ASY_DPP_MAX0_STEP(v, 0x111);  // row_shr:1
+    ASY_DPP_MAX0_STEP(v, 0x112);  // row_shr:2
+    ASY_DPP_MAX0_STEP(v, 0x114);  // row_shr:4
+    ASY_DPP_MAX0_STEP(v, 0x118);  // row_shr:8
+    ASY_DPP_MAX0_STEP(v, 0x142);  // row_bcast:15
+    ASY_DPP_MAX0_STEP(v, 0x143);  // row_bcast:31
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline float wave_max_nonneg_dpp(float v)
+{
+#define ASY_DPP_MAX0_STEP_F32(ctrl)                                                             \
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xf, 0xf, true)))
+    ASY_DPP_MAX0_STEP_F32(0x111);
+    ASY_DPP_MAX0_STEP_F32(0x112);
+    ASY_DPP_MAX0_STEP_F32(0x114);
+    ASY_DPP_MAX0_STEP_F32(0x118);
+    ASY_DPP_MAX0_STEP_F32(0x142);
+    ASY_DPP_MAX0_STEP_F32(0x143);
+#undef ASY_DPP_MAX0_STEP_F32
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // The same for float.
 __device__ inline float wave_max_dpp(float v)
 {

@@ -11,7 +11,10 @@
 // which lane's column, and the order of the rows within a lane (each row is
 // still summed in its own order into its own cell).  A seeded simulated
 // annealing over these three minimises the summed cycles of all gather
-// half-instructions.  The result is deterministic for a given input.
+// half-instructions.  Two constraints keep the packing's one-factor blocks
+// intact: columns move only between the halves of one wave, and rows swap
+// only with rows of the same class.  The result is deterministic for a given
+// input.
 #pragma once
 
 #include <algorithm>
@@ -29,11 +32,14 @@ struct LayoutProblem {
     std::vector<std::vector<std::pair<int, int>>> rows;
     std::vector<int> padded;               // per row: its slot count
     std::vector<std::vector<int>> lane_rows;  // per lane: its rows in slot order
+    std::vector<int> lane_start;              // per lane: slot of its first row (padding before)
+    std::vector<int> row_class;               // per row: rows swap only within a class
 };
 
 struct LayoutResult {
     std::vector<int> cell_of_species;         // [N]: Y cell of each species
     std::vector<std::vector<int>> lane_rows;  // per physical lane: rows in slot order
+    std::vector<int> lane_start;              // per physical lane: slot of its first row
     int64_t cycles_before = 0, cycles_after = 0;  // modelled gather half-instruction cycles
 };
 
@@ -95,8 +101,11 @@ class GatherAnneal {
         LayoutResult r;
         r.cell_of_species.assign(place_.begin(), place_.begin() + N_);
         r.lane_rows.assign(L_, {});
-        for (int k = 0; k < L_; ++k)
+        r.lane_start.assign(L_, 0);
+        for (int k = 0; k < L_; ++k) {
             r.lane_rows[pos_[k]] = lr_[k];
+            r.lane_start[pos_[k]] = p_.lane_start[k];
+        }
         r.cycles_before = before;
         r.cycles_after = total_;
         return r;
@@ -132,7 +141,7 @@ class GatherAnneal {
     {
         std::vector<int> &c = col_[k];
         std::fill(c.begin(), c.end(), N_);
-        int s = 0;
+        int s = p_.lane_start[k];
         for (int r : lr_[k]) {
             const auto &t = p_.rows[r];
             for (size_t e = 0; e < t.size(); ++e) {
@@ -235,7 +244,7 @@ class GatherAnneal {
             return;
         const int k1 = (int)(next() % L_), k2 = (int)(next() % L_);
         const int h1 = pos_[k1] / kHalf, h2 = pos_[k2] / kHalf;
-        if (h1 == h2)
+        if (h1 == h2 || pos_[k1] / 64 != pos_[k2] / 64)
             return;
         move_lane(k1, h1, h2);
         move_lane(k2, h2, h1);
@@ -279,7 +288,7 @@ class GatherAnneal {
         if (n < 2)
             return;
         const int u = (int)(next() % n), v = (int)(next() % n);
-        if (u == v)
+        if (u == v || p_.row_class[lr_[k][u]] != p_.row_class[lr_[k][v]])
             return;
         const std::vector<int> before = col_[k];
         std::swap(lr_[k][u], lr_[k][v]);

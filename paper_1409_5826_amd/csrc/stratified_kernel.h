@@ -49,6 +49,8 @@ struct StratNetwork {
                                // zl + m * lanes at zl * SPL + m), split_first and split_src
     int32_t feat;              // LDS byte address of the learned controller's input and layers
     uint64_t end_mask;         // bit b: some lane ends a row in block b (slots 4b..4b+3)
+    uint32_t one_waves;        // bit w: every term of wave w has the 1.0 cell as second factor
+                               // (no second gathers, no multiplies by 1.0)
     const uint32_t *desc;      // [C][lanes]: LDS byte address of Y[x] | that of Y[y] << 16,
                                // bit 31 set in slot 4b when the lane ends a row in block b
     const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
@@ -196,6 +198,11 @@ struct LearnArgs {
     unsigned long long *count;  // records taken (may exceed capacity)
     int32_t stride;      // record every stride-th accepted state
     int32_t trace_zones; // only zones below this index record
+};
+
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
 };
 
 template <int W>
@@ -386,6 +393,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                 feat[c] = 0.0f;
         }
         const uint64_t emask = sn.end_mask;
+        // every term of this wave has the 1.0 cell as second factor (a uniform value)
+        const bool one_wave = (sn.one_waves >> __builtin_amdgcn_readfirstlane(wave)) & 1u;
         constexpr int NB = C / 4;
         constexpr int kDescAhead = 4;    // descriptor prefetch distance, in blocks of 4 slots
         constexpr int kGatherAhead = GA; // abundance-gather distance, in blocks
@@ -422,12 +431,16 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             // up to b+kGatherAhead and the descriptors of block b+kDescAhead are
             // in flight; the first kDescAhead blocks' descriptors of a step are
             // loaded during the previous step's update.
-            {
+            // one copy of the slot phase per kind of wave: where every second factor is
+            // the 1.0 cell, no second gathers and no products by 1.0 (exact)
+            auto slot_phase = [&](auto one_tag) {
+                constexpr bool ONE = decltype(one_tag)::value;
                 T gx[C], gy[C];
 #pragma unroll
                 for (int s = 0; s < 4 * kGatherAhead && s < C; ++s) {
                     gx[s] = lds_ld<T>(dq[s] & 0xffffu);
-                    gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
+                    if constexpr (!ONE)
+                        gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
                 }
                 T acc = (T)0.0;
                 uint32_t wp = wbase;
@@ -439,11 +452,16 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
 #pragma unroll
                     for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s) {
                         gx[s] = lds_ld<T>(dq[s] & 0xffffu);
-                        gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
+                        if constexpr (!ONE)
+                            gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
                     }
 #pragma unroll
-                    for (int s = 4 * b; s < 4 * b + 4; ++s)
-                        acc = acc + (kr[s] * gx[s]) * gy[s];
+                    for (int s = 4 * b; s < 4 * b + 4; ++s) {
+                        if constexpr (ONE)  // second factor 1.0: the product by 1.0 is exact
+                            acc = acc + kr[s] * gx[s];
+                        else
+                            acc = acc + (kr[s] * gx[s]) * gy[s];
+                    }
                     if ((emask >> b) & 1u) {
                         if ((int32_t)dq[4 * b] < 0) {
                             lds_st<T>(wp, acc);
@@ -452,7 +470,11 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         }
                     }
                 }
-            }
+            };
+            if (one_wave)
+                slot_phase(BoolTag<true>{});
+            else
+                slot_phase(BoolTag<false>{});
             // descriptors of the first blocks of the next step
             {
                 int doff = 0;
@@ -525,7 +547,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             }
             if (bad)
                 rloc = (T)INFINITY;
-            double r = (double)wave_max_dpp(rloc);
+            double r = (double)wave_max_nonneg_dpp(rloc);
             if constexpr (W > 1) {
                 if (lane == 0)
                     xw_r[wave] = r;
@@ -573,7 +595,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                                 ksum += kh;
                             }
                         }
-                        kmax = wave_max_dpp(kmax);
+                        kmax = wave_max_nonneg_dpp(kmax);
                         ksum = wave_sum_dpp(ksum);
                         if constexpr (W > 1) {
                             zone_sync<W>();
