@@ -483,6 +483,8 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         sn.feat = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
         sn.end_mask = end_mask;
         sn.one_waves = one_waves;
+        // single precision: a lane's second and later Y cells start at the first one-factor wave
+        sn.rot = (p == 1 && one_waves) ? (lanes - 64 * __builtin_ctz(one_waves)) % lanes : 0;
         sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc[p]);
         sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
         sn.cell_species = reinterpret_cast<const int32_t *>(base + o_cspec);

@@ -45,10 +45,11 @@ struct StratNetwork {
     int32_t n_reactions;
     int32_t n_slots;           // slots used (<= compile-time C)
     int32_t xch;               // LDS byte address of the exchange area (after the zone's cells)
-    int32_t tab;               // LDS byte address of species_out (lane-major: species
-                               // zl + m * lanes at zl * SPL + m), split_first and split_src
+    int32_t tab;               // LDS byte address of species_out (lane-major: the entry of
+                               // the lane's m-th Y cell at zl * SPL + m), split_first, split_src
     int32_t feat;              // LDS byte address of the learned controller's input and layers
     uint64_t end_mask;         // bit b: some lane ends a row in block b (slots 4b..4b+3)
+    int32_t rot;               // rotation of the lanes' second and later Y cells
     uint32_t one_waves;        // bit w: every term of wave w has the 1.0 cell as second factor
                                // (no second gathers, no multiplies by 1.0)
     const uint32_t *desc;      // [C][lanes]: LDS byte address of Y[x] | that of Y[y] << 16,
@@ -276,6 +277,15 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     float &xw_o = *reinterpret_cast<float *>(xb + 84);
     float *feat = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + sn.feat);
     float *hs = feat + kMlpInPad;  // [2 * kMlpHid]
+    // Y cells of the lane: zl + m * lanes; in single precision m * lanes + ((zl + rot) mod lanes)
+    // for m > 0, so that the cells past the first lanes-many go first to the one-factor waves
+    // (the lighter ones; measured faster in single precision, slower in double)
+    auto cell_at = [&](int m) {
+        if constexpr (sizeof(T) == 4)
+            return m == 0 ? zl : m * LANES + ((zl + sn.rot) & (LANES - 1));
+        else
+            return zl + m * LANES;
+    };
     // the lane's first row-sum cell; its species' F+ / k cells, read from LDS where
     // needed (held in registers across the step loop they would spill), lane-major
     // so that one read fetches all of a lane's entries
@@ -285,7 +295,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     uint32_t *tab_src = reinterpret_cast<uint32_t *>(tab_first + sn.n_split + 1);
 #pragma unroll
     for (int m = 0; m < SPL; ++m) {
-        const int i = zl + m * LANES;
+        const int i = cell_at(m);
         tab_species[zl * SPL + m] = i < N ? sn.species_out[i] : 0u;
     }
     if (sn.n_split > 0) {
@@ -343,7 +353,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         const double *Yz = za.Y + (size_t)z * N;
 #pragma unroll
         for (int m = 0; m < SPL; ++m) {
-            const int i = zl + m * LANES;  // Y cell
+            const int i = cell_at(m);  // Y cell
             if (i < N) {
                 const double y = Yz[sn.cell_species[i]];
                 Y[i] = (T)y;
@@ -526,7 +536,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             }
 #pragma unroll
             for (int m = 0; m < SPL; ++m) {
-                const int i = zl + m * LANES;
+                const int i = cell_at(m);
                 yn[m] = (T)0.0;
                 if (i < N) {
                     const T fp = fpv[m];
@@ -560,7 +570,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             if (r <= o.tol) {
 #pragma unroll
                 for (int m = 0; m < SPL; ++m) {
-                    const int i = zl + m * LANES;
+                    const int i = cell_at(m);
                     if (i < N)
                         Y[i] = yn[m];
                 }
@@ -585,7 +595,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         double kmax = 0.0, ksum = 0.0;
 #pragma unroll
                         for (int m = 0; m < SPL; ++m) {
-                            const int i = zl + m * LANES;
+                            const int i = cell_at(m);
                             if (i < N) {
                                 const double y = yn[m];
                                 feat[sn.cell_species[i]] =
@@ -686,7 +696,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         double *Yo = za.Y + (size_t)z * N;
 #pragma unroll
         for (int m = 0; m < SPL; ++m) {
-            const int i = zl + m * LANES;
+            const int i = cell_at(m);
             if (i < N)
                 Yo[sn.cell_species[i]] = (double)Y[i];
         }
