@@ -163,18 +163,16 @@ int w_index(int W) { return W == 1 ? 0 : (W == 2 ? 1 : 2); }
 // once per process on the kernels' attributes.
 asy_status check_strat_lds_base()
 {
-    static int checked = 0;  // 0 not yet, 1 good, -1 bad
-    if (checked == 0) {
-        checked = 1;
+    static const bool good = [] {  // initialised once, thread-safe
         for (const auto &in : kStratInstances) {
             hipFuncAttributes a{};
             if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(in.fn)) != hipSuccess ||
                 a.sharedSizeBytes != 0)
-                checked = -1;
+                return false;
         }
-    }
-    return checked == 1 ? ASY_OK
-                        : fail(ASY_EDEVICE, "variant 1 kernels must not use static LDS");
+        return true;
+    }();
+    return good ? ASY_OK : fail(ASY_EDEVICE, "variant 1 kernels must not use static LDS");
 }
 
 // Rows of the network: row i (< N) sums the creation flux of species i, row

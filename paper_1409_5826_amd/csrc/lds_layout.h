@@ -6,7 +6,8 @@
 // of 32 lanes; a half takes as many cycles as the most distinct addresses
 // that fall on one of the 64 four-byte banks (equal addresses are broadcast),
 // so with 8-byte cells two different cells collide when their indices agree
-// modulo 32.  The packing leaves three things free that change nothing in the
+// modulo 32.  A 4-byte read is served the same way over 32 banks, so 4-byte
+// cells collide under the same rule and one placement serves both precisions.  The packing leaves three things free that change nothing in the
 // arithmetic: which Y cell holds which species, which physical lane holds
 // which lane's column, and the order of the rows within a lane (each row is
 // still summed in its own order into its own cell).  A seeded simulated

@@ -1,8 +1,8 @@
 """The bank-aware layout of the packed-rows gathers (host code, lds_layout.h), on the CPU.
 
 * The bank model is pinned to conflict counts measured on the device (SQ_LDS_BANK_CONFLICT per
-  8-byte read instruction, tests/golden/lds_bank_conflicts.json): this file's model, written from
-  the measured rules, reproduces every measured count.
+  8- and 4-byte read instruction, tests/golden/lds_bank_conflicts.json): this file's model, written
+  from the measured rules, reproduces every measured count.
 * The optimiser only rearranges: its Y cells are a permutation of the species, every physical lane
   holds one input column (same rows, same start slot, same wave), rows keep their class sequence.
 * Its reported cycles equal this file's independent evaluation of the model, before and after, and
@@ -38,6 +38,17 @@ def instruction_cycles(addresses):
     return sum(half_cycles(addresses[h:h + 32]) for h in range(0, len(addresses), 32))
 
 
+def half_cycles_b32(addresses):
+    """4-byte reads: 32 lanes per half as well, on 32 four-byte banks."""
+    per_bank = Counter((a // 4) % 32 for a in set(int(v) for v in addresses))
+    return max(per_bank.values())
+
+
+def instruction_cycles_b32(addresses):
+    addresses = list(addresses)
+    return sum(half_cycles_b32(addresses[h:h + 32]) for h in range(0, len(addresses), 32))
+
+
 GENERATORS = {
     "consecutive8": lambda l: 8 * l,
     "broadcast": lambda l: 0,
@@ -55,6 +66,19 @@ GENERATORS = {
     "stride8_mod256B": lambda l: 8 * (l % 32),
 }
 
+GENERATORS_B32 = {
+    "f_consecutive4": lambda l: 4 * l,
+    "f_stride8": lambda l: 8 * l,
+    "f_stride128": lambda l: 128 * l,
+    "f_stride256": lambda l: 256 * l,
+    "f_half32_samebanks": lambda l: 4 * (l % 32) + 4096 * (l // 32),
+    "f_half32_other": lambda l: 4 * (l % 32) + 128 * (l // 32),
+    "f_quarter16_samebanks": lambda l: 4 * (l % 16) + 4096 * (l // 16),
+    "f_pairs_samebank": lambda l: 4 * (l // 2) + 4096 * (l % 2),
+    "f_lanes_0_32": lambda l: 4 * (l % 64) + (4096 - 128 if l >= 32 else 0),
+    "f_broadcast": lambda l: 0,
+}
+
 
 def test_bank_model_reproduces_measured_conflicts():
     g = json.load(open(GOLDEN))
@@ -63,6 +87,20 @@ def test_bank_model_reproduces_measured_conflicts():
         assert instruction_cycles(addr) - 2 == case["conflict_cycles"], case["pattern"]
     for case in g["random_cases"]:
         assert instruction_cycles(case["addresses"]) - 2 == case["conflict_cycles"]
+    for case in g["cases_b32"]:
+        addr = [GENERATORS_B32[case["pattern"]](l) for l in range(64)]
+        assert instruction_cycles_b32(addr) - 2 == case["conflict_cycles"], case["pattern"]
+    for case in g["random_cases_b32"]:
+        assert instruction_cycles_b32(case["addresses"]) - 2 == case["conflict_cycles"]
+
+
+def test_cells_collide_alike_in_both_precisions():
+    # 8-byte cells at 8c and 4-byte cells at 4c conflict exactly when c agrees modulo 32,
+    # so one placement serves both precisions
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        cells = rng.integers(0, 400, 32)
+        assert half_cycles(8 * cells) == half_cycles_b32(4 * cells)
 
 
 # ---- problems ---------------------------------------------------------------------------------
