@@ -162,7 +162,9 @@ void asy_options_default(asy_options *o);
  * device call failed.  Creation also lays out variant 1 for 1, 2 and 4
  * waves per zone (row packing and a bank-aware placement of the gathers,
  * a seeded search of about 0.4 s of host time per layout at 150 species);
- * the layout never changes results, only their speed.
+ * the plain controller's results do not depend on the layout, only its
+ * speed does (the learned controller's features sum over species in lane
+ * order, so its proposals may differ in the last bits between layouts).
  */
 asy_status asy_network_create(const asy_network_desc *desc, asy_network **out);
 
