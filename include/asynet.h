@@ -205,6 +205,28 @@ asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_
 /* Current launch configuration of a handle.  cfg: host, out. */
 asy_status asy_get_launch(const asy_network *net, asy_launch *cfg);
 
+/* Layout of variant 1 for one choice of threads per zone (host information). */
+typedef struct {
+    int32_t available;          /* 1 if variant 1 can run with this many threads per zone */
+    int32_t slots;              /* compiled slots per lane (C) */
+    int32_t slots_used;         /* slots per lane the packing needs */
+    int32_t species_per_lane;   /* Y cells per lane in the update */
+    int32_t split_rows;         /* rows summed in chunks (split_above) */
+    uint32_t one_factor_waves;  /* bit w: every term of wave w has 1.0 as second factor, so the
+                                   wave skips the second gathers and the products by 1.0 */
+    int64_t gather_cycles_packed;  /* modelled LDS cycles of one zone-step's gathers (the gfx950
+                                      bank rules) in packing order ... */
+    int64_t gather_cycles_placed;  /* ... and after the bank-aware placement */
+} asy_layout_info;
+
+/*
+ * The variant-1 layout built at creation for threads_per_zone (64, 128 or
+ * 256; ASY_EINVAL otherwise).  Host only, no device call.  info: host, out;
+ * available = 0 (and the rest zero) when no compiled instance holds it.
+ */
+asy_status asy_network_layout_info(const asy_network *net, int32_t threads_per_zone,
+                                   asy_layout_info *info);
+
 /*
  * Set the launch configuration (validated against the device limits and the
  * network's LDS footprint; ASY_EINVAL if it cannot run).  The results of

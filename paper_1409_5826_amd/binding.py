@@ -46,6 +46,7 @@ EXPORTS = (
     "asy_integrate_batch_trace",
     "asy_probe_lds_bandwidth",
     "asy_integrate_schedule",
+    "asy_network_layout_info",
 )
 
 MLP_N_IN = 166
@@ -103,6 +104,22 @@ class asy_launch(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class asy_layout_info(C.Structure):
+    _fields_ = [
+        ("available", C.c_int32),
+        ("slots", C.c_int32),
+        ("slots_used", C.c_int32),
+        ("species_per_lane", C.c_int32),
+        ("split_rows", C.c_int32),
+        ("one_factor_waves", C.c_uint32),
+        ("gather_cycles_packed", C.c_int64),
+        ("gather_cycles_placed", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -124,6 +141,8 @@ def lib():
         L.asy_integrate_batch.restype = I32
         L.asy_get_launch.argtypes = [P, C.POINTER(asy_launch)]
         L.asy_get_launch.restype = I32
+        L.asy_network_layout_info.argtypes = [P, I32, C.POINTER(asy_layout_info)]
+        L.asy_network_layout_info.restype = I32
         L.asy_set_launch.argtypes = [P, C.POINTER(asy_launch)]
         L.asy_set_launch.restype = I32
         L.asy_autotune.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, C.POINTER(asy_launch)]
@@ -421,6 +440,12 @@ class Network:
 
     def get_launch(self) -> dict:
         return asy_get_launch(self.handle).as_dict()
+
+    def layout_info(self, threads_per_zone: int) -> dict:
+        info = asy_layout_info()
+        _check(lib().asy_network_layout_info(self.handle, int(threads_per_zone), C.byref(info)),
+               "asy_network_layout_info")
+        return info.as_dict()
 
 
 class Mlp:

@@ -1152,6 +1152,28 @@ asy_status asy_get_launch(const asy_network *net, asy_launch *cfg)
     return ASY_OK;
 }
 
+asy_status asy_network_layout_info(const asy_network *net, int32_t threads_per_zone,
+                                   asy_layout_info *info)
+{
+    if (!net || !info)
+        return fail(ASY_EINVAL, "net and info must be non-NULL");
+    if (threads_per_zone != 64 && threads_per_zone != 128 && threads_per_zone != 256)
+        return fail(ASY_EINVAL, "threads_per_zone must be 64, 128 or 256");
+    const StratLayout &L = net->strat[w_index(threads_per_zone / 64)];
+    *info = asy_layout_info{};
+    if (!L.ok)
+        return ASY_OK;
+    info->available = 1;
+    info->slots = L.C;
+    info->slots_used = L.C_needed;
+    info->species_per_lane = L.SPL;
+    info->split_rows = L.n_split;
+    info->one_factor_waves = L.one_waves;
+    info->gather_cycles_packed = L.gather_cycles_before;
+    info->gather_cycles_placed = L.gather_cycles_after;
+    return ASY_OK;
+}
+
 asy_status asy_set_launch(asy_network *net, const asy_launch *cfg)
 {
     if (!net || !cfg)

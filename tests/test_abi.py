@@ -93,3 +93,9 @@ def test_null_arguments():
     assert L.asy_get_launch(None, None) == binding.ASY_EINVAL
     L.asy_network_destroy(None)   # no-op
     assert binding.asy_version().startswith("asynet")
+
+
+def test_layout_info_argument_errors():
+    L = binding.lib()
+    info = binding.asy_layout_info()
+    assert L.asy_network_layout_info(None, 128, C.byref(info)) == binding.ASY_EINVAL

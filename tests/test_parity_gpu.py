@@ -235,3 +235,21 @@ def test_zero_zones_is_a_no_op():
         torch.cuda.synchronize()
     finally:
         net.close()
+
+
+def test_layout_info_one_factor_waves_and_placement():
+    # the packing frees whole waves of second gathers and the placement lowers the modelled
+    # gather cycles; the integrations above run through these layouts
+    cases = [("n150_r1604_arrhenius", 128, 0b10), ("n365_r4400_arrhenius", 256, 0b1100)]
+    for name, tpz, waves in cases:
+        net = binding.Network(workloads.preset(name, n_zones=1).network)
+        try:
+            info = net.layout_info(tpz)
+            say(f"layout {name} {tpz}: {info}")
+            assert info["available"] == 1 and info["slots_used"] <= info["slots"]
+            assert info["one_factor_waves"] == waves
+            assert info["gather_cycles_placed"] < info["gather_cycles_packed"]
+            with pytest.raises(binding.AsyError):
+                net.layout_info(96)
+        finally:
+            net.close()
