@@ -253,3 +253,23 @@ def test_layout_info_one_factor_waves_and_placement():
                 net.layout_info(96)
         finally:
             net.close()
+
+
+@pytest.mark.parametrize("tpz", [64, 128])
+def test_one_body_network_every_wave_one_factor(tpz):
+    # only one-body reactions: every second factor is the 1.0 cell, so every wave takes the
+    # slot phase without second gathers; constant rates, bit for bit with the oracle
+    net = workloads.make_network(72, 200, 0, mass_group=8, seed=7701)
+    zones = workloads.make_zones(net, 12, seed=7702, t_end=1e-2, log10_k_range=(-4.0, 6.0))
+    wl = workloads.Workload("one_body_n72", net, zones, 0.01, "one-body only")
+    say(f"case one-body n72 zones=12 threads_per_zone={tpz}")
+    h = binding.Network(net)
+    try:
+        info = h.layout_info(tpz)
+    finally:
+        h.close()
+    assert info["one_factor_waves"] == (1 << (tpz // 64)) - 1
+    g = run_gpu(wl, launch=dict(variant=1, threads_per_zone=tpz, zone_order=1))
+    ref = oracle.integrate_batch(net, zones)
+    assert compare(g, ref)["bit_exact_zones"] == 1.0
+    np.testing.assert_array_equal(g["n_accepted"], ref["n_acc"])
