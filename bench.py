@@ -223,6 +223,8 @@ def main(argv=None):
             "accepted_zone_steps": acc_per_step,
             "rejected_zone_steps": att_per_step - acc_per_step,
             "launch": net.get_launch(),
+            "layout": (net.layout_info(net.get_launch()["threads_per_zone"])
+                       if net.get_launch()["variant"] == 1 else None),
             "parallelism": "1 GPU",
         },
         "roofline": {
