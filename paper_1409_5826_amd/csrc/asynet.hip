@@ -201,7 +201,11 @@ constexpr int64_t kLayoutIters = 100000;  // annealing moves per layout (~0.4 s 
 
 // Pack the rows onto 64*W lanes: every row padded to a multiple of 4 terms
 // (at least 4, so that an empty row still writes its 0.0), longest first,
-// each onto the lane with the least work so far (lowest lane on ties).
+// each onto the lane with the least work so far (lowest lane on ties); the
+// slot count C is the smallest compiled one that holds this packing.  Within
+// that C, a second packing frees whole waves of second gathers when it can
+// (below).  Then the bank-aware placement (lds_layout.h) picks the Y cells,
+// the lanes' order within each wave and the rows' order within each lane.
 // Row sums take the cells after Y in lane order (lane 0's rows first, each
 // lane's in its slot order); split rows' totals follow.  Leaves L.ok false
 // when no compiled instance can hold the layout.

@@ -13,9 +13,12 @@
 // The host pads every row to a multiple of 4 terms with zero-rate terms
 // (adding +0.0 leaves a sum unchanged) and packs the 2N rows onto the 64*W
 // lanes of a zone's workgroup, longest first, each onto the lane with the
-// least work so far.  A lane's column is the concatenation of its rows, so a
-// row ends at the end of a block of 4 slots, at a different block on each
-// lane.  The sums land in the LDS cells after Y in lane order -- lane l's k-th
+// least work so far -- or, where that frees whole waves, the rows with a
+// second factor other than ONE first-fit onto the first lanes, so that the
+// remaining waves hold only terms (k_j * Y[x]) * 1.0 and run a copy of the
+// slot phase without the second gather and the product by 1.0 (exact).  A
+// lane's column is its padding, then its rows back to back, so a row ends at
+// the end of a block of 4 slots, at a different block on each lane.  The sums land in the LDS cells after Y in lane order -- lane l's k-th
 // row in cell lane_out[l] + k -- so a lane needs only one bit per block, set
 // in the first descriptor of the block where one of its rows ends, and a
 // running cell address; a uniform mask (end_mask, bit b: some lane ends a row
