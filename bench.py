@@ -111,7 +111,7 @@ def main(argv=None):
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(zones shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+              "(zones are independent: they would shard across GPUs with no exchange)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -51,7 +51,7 @@ typedef enum {
     ASY_EINVAL = -1,  /* invalid argument or descriptor */
     ASY_ENOMEM = -2,  /* device or host allocation failed */
     ASY_EDEVICE = -3, /* HIP runtime error, or no usable gfx950 device */
-    ASY_ENOTSUP = -4, /* valid request this build does not support */
+    ASY_ENOTSUP = -4, /* valid request the library does not support */
     ASY_ESTATE = -5   /* call out of order (e.g. learned controller before asy_set_mlp) */
 } asy_status;
 

@@ -3,10 +3,11 @@
 A multilayer perceptron 166 -> 128 -> 128 -> 1 with ReLU hidden layers maps
 features of a zone's accepted state to o, the predicted log2 of the ratio of
 the next accepted step to the last one.  The paper has no learned
-controller; this network, its features and its training follow the
-specification of the learned-timestep form of this build (see the design
-notes), in plain numpy FP64 with BF16 rounding applied at exactly the points
-where the GPU kernels feed their matrix cores:
+controller; this network, its features and its training are the library's
+learned-timestep form (features: log10 abundances, the largest and mean
+depletion rate times the step, the step and the tolerance), written here in
+plain numpy FP64 with BF16 rounding applied at exactly the points where the
+GPU kernels feed their matrix cores:
 
   forward   xb = bf16(x), W*b = bf16(W*)
             a1 = xb W1b + b1,  h1b = bf16(relu(a1))

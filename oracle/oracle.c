@@ -12,9 +12,9 @@
  * no blocking and no reordering.  Build with -ffp-contract=off so that no
  * multiply-add is fused: every expression rounds exactly as written.
  *
- * Readings where the paper is silent (the timestep controller, the tie at
- * k*dt == kappa, the clipping at the end of the interval) are the ones listed
- * in the design notes of this repository; each is marked "reading" below.
+ * Where the paper is silent (the timestep controller, the tie at
+ * k*dt == kappa, the clipping at the end of the interval) this file takes an
+ * explicit reading, stated where it is used and marked "reading" below.
  */
 #include <math.h>
 #include <stdint.h>
