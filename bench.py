@@ -104,7 +104,7 @@ def main(argv=None):
                     help="skip the single-precision measurement of the same workload")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposer comparison")
-    ap.add_argument("--learned-zones", type=int, default=64)
+    ap.add_argument("--learned-zones", type=int, default=4096)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args(argv)
