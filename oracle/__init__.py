@@ -45,25 +45,45 @@ def options(**kw) -> Options:
     return Options(**d)
 
 
+# gcc flags of every build: no fused multiply-add contraction, no value-changing
+# optimisation (the arithmetic is evaluated as written, in order)
+_CFLAGS = ["-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so with gcc (no FMA contraction)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-fopenmp", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        cmd = ["gcc", "-O2", *_CFLAGS, _SRC, "-o", _LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
 
 
+def build_for_this_host(path: str) -> str:
+    """Compile a copy of the oracle for timing on the machine that runs it: -O3 and
+    -march=native on top of the flags above (same arithmetic, same results), written to path."""
+    cmd = ["gcc", "-O3", "-march=native", *_CFLAGS, _SRC, "-o", path + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(path + ".tmp", path)
+    return path
+
+
 _lib = None
+_lib_path = _LIB
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from path (a build_for_this_host copy) from now on."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_lib_path):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(_lib_path)
         P = C.c_void_p
         L.orc_rates_arrhenius.argtypes = [C.c_int32, P, P, C.c_double, P]
         L.orc_rhs.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P]
@@ -89,6 +109,10 @@ def lib():
                                                C.POINTER(Options), C.c_int32]
         L.orc_mlp_forward.argtypes = [P, P]
         L.orc_mlp_forward.restype = C.c_double
+        L.orc_mlp_forward_mfma.argtypes = [P, P]
+        L.orc_mlp_forward_mfma.restype = C.c_float
+        L.orc_mfma_dot.argtypes = [C.c_float, P, P, C.c_int32]
+        L.orc_mfma_dot.restype = C.c_float
         L.orc_mlp_features.argtypes = [C.c_int32, P, P, C.c_double, C.c_double, P]
         L.orc_integrate_zone_learned.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_double, P,
                                                  C.POINTER(Options), C.c_int32, P, P, C.c_int64,
@@ -117,7 +141,8 @@ class _Trace(C.Structure):
 
 class _LearnLog(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("count", C.c_int64), ("q", C.c_void_p),
-                ("feat", C.c_void_p), ("label", C.c_void_p), ("n_acc", C.c_void_p)]
+                ("feat", C.c_void_p), ("label", C.c_void_p), ("n_acc", C.c_void_p),
+                ("label_stride", C.c_int64)]
 
 
 def rates_arrhenius(A, E, T) -> np.ndarray:
@@ -247,6 +272,22 @@ def mlp_forward_c(params, x) -> float:
     return float(lib().orc_mlp_forward(_p(p), _p(xv)))
 
 
+def mlp_forward_mfma(params, x) -> float:
+    """The network output in the device's matrix-core arithmetic (FP32 accumulation by the
+    measured gfx950 rule), the value that decides the proposal q."""
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    xv = np.ascontiguousarray(x, dtype=np.float32)
+    return float(lib().orc_mlp_forward_mfma(_p(p), _p(xv)))
+
+
+def mfma_dot(acc, a, b) -> float:
+    """acc + a.b accumulated by the matrix-core rule (len(a) a multiple of 8; a, b values
+    representable in bfloat16)."""
+    a, b = _f64(a), _f64(b)
+    assert len(a) == len(b) and len(a) % 8 == 0
+    return float(lib().orc_mfma_dot(float(np.float32(acc)), _p(a), _p(b), len(a)))
+
+
 def mlp_features(Y, kd, h, tol) -> np.ndarray:
     Y, kd = _f64(Y), _f64(kd)
     x = np.zeros(166, dtype=np.float32)
@@ -255,12 +296,14 @@ def mlp_features(Y, kd, h, tol) -> np.ndarray:
 
 
 def integrate_zone_learned(net, k, Y0, t_end, dt0, params=None, opts: Optional[Options] = None,
-                           learned=True, q_replay=None, log_capacity=0):
+                           learned=True, q_replay=None, log_capacity=0, label_stride=1):
     """One zone with the learned (or, learned=False, the plain) controller.
 
     q_replay (optional) supplies the first 32 q values in place of the network.
     With log_capacity > 0 the result holds, per proposal point, q (None for the
-    plain controller), the features, the label and the accepted-step count.
+    plain controller), the features, the label (the boundary-step label, computed
+    at points whose accepted-step count is a multiple of label_stride, else NaN)
+    and the accepted-step count.
     """
     opts = opts or options()
     a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
@@ -276,7 +319,8 @@ def integrate_zone_learned(net, k, Y0, t_end, dt0, params=None, opts: Optional[O
     lf = np.zeros((max(cap, 1), 166), np.float32)
     ll = np.zeros(max(cap, 1), np.float64)
     ln = np.zeros(max(cap, 1), np.int64)
-    lg = _LearnLog(cap, 0, lq.ctypes.data, lf.ctypes.data, ll.ctypes.data, ln.ctypes.data)
+    lg = _LearnLog(cap, 0, lq.ctypes.data, lf.ctypes.data, ll.ctypes.data, ln.ctypes.data,
+                   int(label_stride))
     na, nr = np.zeros(1, np.int64), np.zeros(1, np.int64)
     st = lib().orc_integrate_zone_learned(net.n_species, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y),
                                           float(t_end), _p(dt), C.byref(opts), int(bool(learned)),

@@ -45,7 +45,9 @@ MUTATIONS = {
 LEARNED_MUTATIONS = {
     "learned_no_plain_fallback": ("                step = plain_step;", "                step = h * 0.5;"),
     "learned_mean_feature_unscaled": ("fmax(ksum / n_species, 1e-300)", "fmax(ksum, 1e-300)"),
-    "learned_label_inverted": ("log2(h / h_prev)", "log2(h_prev / h)"),
+    "learned_label_no_safety": ("log2(o->safety) + lo / 32.0", "lo / 32.0"),
+    "learned_label_against_new_state": ("orc_change(n_species, Y, Yn, o->y_floor) <= o->tol",
+                                        "orc_change(n_species, Yn, Y, o->y_floor) <= o->tol"),
     "learned_bias_dropped": ("        a += b2[j];\n", "\n"),
     "learned_relu_before_bias": ("        a += b1[j];\n        h1[j] = orc_bf16(a > 0.0 ? a : 0.0);",
                                  "        h1[j] = orc_bf16(a > 0.0 ? a : 0.0) + b1[j];"),
