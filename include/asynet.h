@@ -113,7 +113,8 @@ typedef struct {
 typedef struct {
     double kappa;      /* stiffness switch; 1.0 */
     double tol;        /* relative-change bound; 0.01 */
-    double y_floor;    /* abundance floor of the change measure; 1e-10 */
+    double y_floor;    /* abundance floor of the change measure; 1e-10 (>= FLT_MIN, the
+                          smallest normal float, with ASY_PREC_F32; else ASY_EINVAL) */
     double grow_max;   /* 2.0 */
     double safety;     /* 0.9 */
     double shrink_min; /* 0.1 */
@@ -237,10 +238,14 @@ asy_status asy_set_launch(asy_network *net, const asy_launch *cfg);
 /*
  * Time candidate launch configurations on copies of the first sample_zones
  * zones of the given batch (same arguments as asy_integrate_batch, left
- * unmodified) and keep the fastest: variant 1 with 1, 2 and 4 waves per zone
- * and both zone orders, and variant 0 with 128 and 256 threads (double
- * precision only).  Candidates run in opts->precision with the plain
- * controller.  Synchronous.  best: host, out, may be NULL.
+ * unmodified; every array must hold at least sample_zones zones, which the
+ * library cannot check) and keep the fastest: first variant 1 with 1, 2 and 4
+ * waves per zone and both zone orders, and variant 0 with 128 and 256 threads
+ * (double precision only), one workgroup per zone without graph; then, for the
+ * fastest of those, persistent grids of 1, 2, 3, 4, 6 and 8 workgroups per
+ * compute unit and graph replay, each grid with and without.  Candidates run in
+ * opts->precision with the plain controller, each timed on its second run.
+ * Synchronous.  best: host, out, may be NULL.
  */
 asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sample_zones,
                         const double *Y, const double *T, const double *k_zone,
@@ -310,10 +315,14 @@ asy_status asy_set_mlp(asy_network *net, const asy_mlp *m);
  * asy_integrate_batch_trace: asy_integrate_batch that also writes training
  * records, one per sampled accepted state of zones z < trace_zones (every
  * stride-th accepted step), ASY_TRACE_REC floats each, into trace (device
- * [capacity][ASY_TRACE_REC]): [0, 166) the state's features, [166] the label
- * log2(h_next / h) of the step accepted next (NaN if the zone ended first or
- * that step was clipped to t_end), [167] 32 q of the learned proposal (NaN
- * with the plain controller), [168] zone index, [169] accepted-step index.
+ * [capacity][ASY_TRACE_REC]): [0, 166) the state's features, [166] the
+ * training label log2(safety * h_b / h), where h_b is the largest step of the
+ * grid h 2^(q/32), q = -96..96, from which the controller would accept the
+ * attempt, found by bisection on q assuming acceptance is monotone in the step
+ * (the state's sums once, then one trial update per bisection step; nothing
+ * of the zone changes; NaN when no step of the grid is accepted), [167] 32 q
+ * of the learned proposal (NaN with the plain controller), [168] zone index,
+ * [169] accepted-step index.
  * count (device, in/out) counts records taken; those beyond capacity are
  * dropped.  capacity < 2^31.  Record order is not deterministic.
  */

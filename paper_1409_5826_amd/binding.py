@@ -340,9 +340,13 @@ def asy_autotune(handle, n_species, n_reactions, Y, t_end, dt, T=None, k_zone=No
     import torch
 
     Z = int(Y.shape[0])
+    n_sample = Z if sample_zones is None else int(sample_zones)
+    if not 1 <= n_sample <= Z:
+        # the library copies sample_zones zones out of each array
+        raise ValueError(f"sample_zones must be in [1, {Z}] (the zones in Y), got {n_sample}")
     best = asy_launch()
     st = lib().asy_autotune(
-        handle, None if opts is None else C.byref(opts), Z if sample_zones is None else int(sample_zones),
+        handle, None if opts is None else C.byref(opts), n_sample,
         _dev_ptr(Y, torch.float64, (Z, n_species), "Y"), _dev_ptr(T, torch.float64, (Z,), "T"),
         _dev_ptr(k_zone, torch.float64, (Z, n_reactions), "k_zone"),
         _dev_ptr(t_end, torch.float64, (Z,), "t_end"), _dev_ptr(dt, torch.float64, (Z,), "dt"),

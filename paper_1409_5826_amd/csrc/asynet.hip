@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -84,7 +85,7 @@ struct asy_network {
     void *mlp_block = nullptr;
     MlpDevice mlp{};
     bool has_mlp = false;
-    const double *pow2 = nullptr;  // device [32]: 2^(b/32), in mlp_block
+    const double *pow2 = nullptr;  // device [32]: 2^(b/32), in dev_block
 };
 
 struct asy_mlp {
@@ -194,6 +195,13 @@ std::vector<std::vector<Term>> network_rows(int N, int R, const int32_t *r0, con
             rows[N + b].push_back({j, a, N});
     }
     return rows;
+}
+
+// Term descriptors are stored block-major: the 4 slots of block b of lane l are
+// consecutive, so a lane fetches a block's descriptors with one 16-byte load.
+size_t desc_index(int slot, int lane, int lanes)
+{
+    return ((size_t)(slot / 4) * lanes + lane) * 4 + slot % 4;
 }
 
 constexpr int kSplitAboveDefault = 64;  // rows with more terms are summed in chunks
@@ -402,15 +410,15 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
             for (int row : lane_rows[l]) {
                 const auto &terms = rows[row];
                 for (size_t e = 0; e < terms.size(); ++e) {
-                    const size_t at = (size_t)(start + (int)e) * lanes + l;
-                    desc[p][at] = (uint32_t)cell_of[terms[e].x] * B |
-                                  ((uint32_t)cell_of[terms[e].y] * B << 16);
+                    const int slot = start + (int)e;
+                    desc[p][desc_index(slot, l, lanes)] = (uint32_t)cell_of[terms[e].x] * B |
+                                                          ((uint32_t)cell_of[terms[e].y] * B << 16);
                     if (p == 0)
-                        rx[at] = terms[e].rx;
+                        rx[(size_t)slot * lanes + l] = terms[e].rx;
                 }
                 start += padded(row);
                 const int blk = start / 4 - 1;  // the row ends in this block
-                desc[p][(size_t)(4 * blk) * lanes + l] |= 0x80000000u;
+                desc[p][desc_index(4 * blk, l, lanes)] |= 0x80000000u;
                 end_mask |= 1ull << blk;
             }
             lane_out[p].push_back((uint32_t)lane_first[l] * B);
@@ -432,7 +440,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         bool all = true;
         for (int s = 0; s < C && all; ++s)
             for (int l = 64 * w; l < 64 * w + 64 && all; ++l)
-                all = ((desc[0][(size_t)s * lanes + l] >> 16) & 0x7fffu) == (uint32_t)N * 8u;
+                all = ((desc[0][desc_index(s, l, lanes)] >> 16) & 0x7fffu) == (uint32_t)N * 8u;
         if (all)
             one_waves |= 1u << w;
     }
@@ -561,10 +569,25 @@ hipError_t launch_variant0(asy_network *net, const DevOptions &o, const ZoneArgs
     return hipGetLastError();
 }
 
+// Per-call device scratch: the Arrhenius rates [zones][reactions] of variant 1,
+// the scheduling keys and the longest-first order [zones] (the zone counter
+// travels in ZoneArgs::queue).
+struct CallBufs {
+    double *rates;
+    float *key;
+    int32_t *order;
+};
+
+CallBufs net_bufs(const asy_network *net)
+{
+    return CallBufs{net->rate_buf, net->key_buf, net->order_buf};
+}
+
 // Queue every kernel of one call on stream s (no allocation, no host sync, so
 // the sequence can be captured into a graph).
 hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o,
-                      const ZoneArgs &za, hipStream_t s, int mode = 0, LearnArgs la = LearnArgs{})
+                      const ZoneArgs &za, const CallBufs &cb, hipStream_t s, int mode = 0,
+                      LearnArgs la = LearnArgs{})
 {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, za.queue);
     hipError_t e = hipGetLastError();
@@ -578,43 +601,43 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
             const size_t total = (size_t)za.n_zones * net->n_reactions;
             const int blocks = (int)std::min<size_t>((total + 255) / 256, (size_t)net->n_cu * 16);
             hipLaunchKernelGGL(rates_arrhenius_kernel, dim3(blocks), dim3(256), 0, s, za.n_zones,
-                               net->n_reactions, net->dn.A, net->dn.E, za.T, net->rate_buf);
+                               net->n_reactions, net->dn.A, net->dn.E, za.T, cb.rates);
             e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
-            rates = net->rate_buf;
+            rates = cb.rates;
         }
         const int32_t *order = nullptr;
         if (c.zone_order == 1) {
             const int kb = (int)std::min<size_t>(((size_t)za.n_zones * kWave + 255) / 256,
                                                  (size_t)net->n_cu * 16);
             hipLaunchKernelGGL(zone_cost_kernel, dim3(kb), dim3(256), 0, s, za.n_zones,
-                               net->n_reactions, rates, net->key_buf);
+                               net->n_reactions, rates, cb.key);
             e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
             const int ob = (za.n_zones + kOrderChunk - 1) / kOrderChunk;
-            hipLaunchKernelGGL(zone_order_kernel, dim3(ob), dim3(1024), 0, s, za.n_zones,
-                               net->key_buf, net->order_buf);
+            hipLaunchKernelGGL(zone_order_kernel, dim3(ob), dim3(1024), 0, s, za.n_zones, cb.key,
+                               cb.order);
             e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
-            order = net->order_buf;
+            order = cb.order;
         }
         const StratInstance *inst = find_strat_instance(W, L.SPL, L.C, mode);
         if (!inst)
             return hipErrorInvalidDeviceFunction;
-        if (mode >= 2) {
-            la.mlp = net->mlp;
+        if (mode >= 1 && mode <= 3)
             la.pow2 = net->pow2;
-        }
+        if (mode >= 2)
+            la.mlp = net->mlp;
         const int zpg = c.zones_per_group;
         int grid = (za.n_zones + zpg - 1) / zpg;
         if (c.groups_per_cu > 0)
             grid = std::min(grid, c.groups_per_cu * net->n_cu);
         hipLaunchKernelGGL(inst->fn, dim3(grid), dim3(c.threads_per_zone * zpg),
-                           lds_bytes_variant1(net, W, mode), s, mode == 4 ? L.sn32 : L.sn, o, za, rates,
-                           order, la);
+                           lds_bytes_variant1(net, W, mode), s, mode == 4 ? L.sn32 : L.sn, o, za,
+                           rates, order, la);
         return hipGetLastError();
     }
     int grid = za.n_zones;
@@ -656,6 +679,10 @@ asy_status validate_options(const asy_options *o)
         return fail(ASY_EINVAL, "unknown controller");
     if (o->precision != ASY_PREC_F64 && o->precision != ASY_PREC_F32)
         return fail(ASY_EINVAL, "unknown precision");
+    // single precision rounds y_floor to float: below the smallest normal float it would
+    // lose digits or become 0 (a species at 0 that gains anything then gives r = inf)
+    if (o->precision == ASY_PREC_F32 && !(o->y_floor >= (double)FLT_MIN))
+        return fail(ASY_EINVAL, "single precision needs y_floor >= FLT_MIN (1.17549435e-38)");
     return ASY_OK;
 }
 
@@ -713,7 +740,7 @@ asy_status enqueue(asy_network *net, const asy_launch &c, const DevOptions &o, c
                    hipStream_t s, int mode = 0, const LearnArgs &la = LearnArgs{})
 {
     if (!c.use_graph) {
-        HIP_TRY(launch_all(net, c, o, za, s, mode, la));
+        HIP_TRY(launch_all(net, c, o, za, net_bufs(net), s, mode, la));
         return ASY_OK;
     }
     std::vector<uint8_t> key;
@@ -732,7 +759,7 @@ asy_status enqueue(asy_network *net, const asy_launch &c, const DevOptions &o, c
         if (!net->capture_stream)
             HIP_TRY(hipStreamCreateWithFlags(&net->capture_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(net->capture_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = launch_all(net, c, o, za, net->capture_stream, mode, la);
+        hipError_t le = launch_all(net, c, o, za, net_bufs(net), net->capture_stream, mode, la);
         hipGraph_t graph = nullptr;
         hipError_t ee = hipStreamEndCapture(net->capture_stream, &graph);
         if (le != hipSuccess || ee != hipSuccess) {
@@ -1040,6 +1067,10 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     const bool arr = d->rate_form == ASY_RATES_ARRHENIUS;
     const size_t o_A = arr ? carve(sizeof(double) * R) : 0;
     const size_t o_E = arr ? carve(sizeof(double) * R) : 0;
+    const size_t o_pow2 = carve(sizeof(double) * 32);
+    double pow2_tab[32];  // 2^(b/32): steps h 2^(q/32) of learned proposals and trace labels
+    for (int b = 0; b < 32; ++b)
+        pow2_tab[b] = std::exp2(b / 32.0);
     he = hipMalloc(&net->dev_block, off);
     if (he != hipSuccess) {
         delete net;
@@ -1064,11 +1095,13 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
         put(o_A, d->A, sizeof(double) * R);
         put(o_E, d->E, sizeof(double) * R);
     }
+    put(o_pow2, pow2_tab, sizeof(pow2_tab));
     if (ce != hipSuccess) {
         asy_network_destroy(net);
         return fail(ASY_EDEVICE, std::string("upload: ") + hipGetErrorString(ce));
     }
     net->queue = reinterpret_cast<int32_t *>(base + o_queue);
+    net->pow2 = reinterpret_cast<const double *>(base + o_pow2);
     DevNetwork &dn = net->dn;
     dn.n_species = N;
     dn.n_reactions = R;
@@ -1137,10 +1170,10 @@ void asy_network_destroy(asy_network *net)
             (void)hipFree(L.dev);
     if (net->mlp_block)
         (void)hipFree(net->mlp_block);
-    if (net->rate_buf)
-        (void)hipFree(net->rate_buf);
     if (net->sched_block)
         (void)hipFree(net->sched_block);
+    if (net->rate_buf)
+        (void)hipFree(net->rate_buf);
     if (net->key_buf)
         (void)hipFree(net->key_buf);
     if (net->order_buf)
@@ -1231,8 +1264,6 @@ asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n
                             void *stream, bool trace, LearnArgs la)
 {
     g_last_error.clear();
-    if (!net)
-        return fail(ASY_EINVAL, "net must be non-NULL");
     asy_options o;
     asy_options_default(&o);
     if (opts)
@@ -1240,6 +1271,8 @@ asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n
     asy_status st = validate_options(&o);
     if (st != ASY_OK)
         return st;
+    if (!net)
+        return fail(ASY_EINVAL, "net must be non-NULL");
     if (n_zones < 0)
         return fail(ASY_EINVAL, "n_zones must be >= 0");
     if (trace && (!la.trace || !la.count || la.capacity < 0 || la.capacity > INT32_MAX ||
@@ -1359,7 +1392,7 @@ asy_status asy_integrate_schedule(asy_network *net, const asy_options *opts, int
             HIP_TRY(hipMemcpyAsync(before, Y, nY * 8, hipMemcpyDeviceToDevice, s));
         ZoneArgs za{n_zones, Y, T ? T + (size_t)step * n_zones : nullptr, k_zone,
                     dt_hydro + (size_t)step * n_zones, dt, acc_s, rej_s, st_s, net->queue};
-        HIP_TRY(launch_all(net, net->launch, dev, za, s, mode));
+        HIP_TRY(launch_all(net, net->launch, dev, za, net_bufs(net), s, mode));
         hipLaunchKernelGGL(schedule_step_kernel, dim3(blocks), dim3(256), 0, s, n_zones,
                            net->n_species, step == 0 ? 1 : 0, acc_s, rej_s, st_s, n_accepted,
                            n_rejected, zone_status, Y, before, q,
@@ -1423,13 +1456,13 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
         if (!L.ok || (mode == 4 && (!L.ok32 || !find_strat_instance(W, L.SPL, L.C, 4))))
             continue;
         for (int zo : {1, 0}) {
-            asy_launch c{1, 64 * W, 1, 0, net->launch.use_graph, zo};
+            asy_launch c{1, 64 * W, 1, 0, 0, zo};
             if (validate_launch(net, &c) == ASY_OK)
                 cands.push_back(c);
         }
     }
     for (int nt : {128, 256}) {
-        asy_launch c{0, nt, 1, 0, net->launch.use_graph, 0};
+        asy_launch c{0, nt, 1, 0, 0, 0};
         if (mode == 0 && validate_launch(net, &c) == ASY_OK)
             cands.push_back(c);
     }
@@ -1439,27 +1472,64 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
     asy_launch best_c = saved;
     ZoneArgs za{Z, wY, T, k_zone, t_end, wdt, wacc, wrej, wst, net->queue};
     asy_status result = ASY_OK;
-    for (const asy_launch &c : cands) {
+    // time one candidate: the first run warms up (and captures the graph of a graph launch),
+    // the second is timed; calls go through enqueue like asy_integrate_batch
+    auto time_candidate = [&](const asy_launch &c, float *ms) {
         net->launch = c;
-        st = ensure_call_bufs(net, c, Z, nullptr);
-        float ms = 0.0f;
-        for (int rep = 0; rep < 2 && st == ASY_OK; ++rep) {  // first run warms up
+        asy_status cst = ensure_call_bufs(net, c, Z, nullptr);
+        for (int rep = 0; rep < 2 && cst == ASY_OK; ++rep) {
             if (hipMemcpy(wY, Y, nY * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
                 hipMemcpy(wdt, dt, (size_t)Z * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
-                hipEventRecord(e0, nullptr) != hipSuccess ||
-                launch_all(net, c, to_dev(o), za, nullptr, mode) != hipSuccess ||
-                hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                st = fail(ASY_EDEVICE, "autotune: a candidate launch failed");
+                hipEventRecord(e0, nullptr) != hipSuccess)
+                return fail(ASY_EDEVICE, "autotune: a candidate launch failed");
+            cst = enqueue(net, c, to_dev(o), za, nullptr, mode);
+            if (cst != ASY_OK)
+                return cst;
+            if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+                return fail(ASY_EDEVICE, "autotune: a candidate launch failed");
         }
-        if (st != ASY_OK) {
-            result = st;
-            break;
-        }
-        if (best_ms == 0.0f || ms < best_ms) {
+        return cst;
+    };
+    auto consider = [&](const asy_launch &c) {
+        float ms = 0.0f;
+        asy_status cst = time_candidate(c, &ms);
+        if (cst == ASY_OK && (best_ms == 0.0f || ms < best_ms)) {
             best_ms = ms;
             best_c = c;
         }
+        return cst;
+    };
+    for (const asy_launch &c : cands) {
+        result = consider(c);
+        if (result != ASY_OK)
+            break;
+    }
+    // then, for the best kernel: persistent grids of 1..8 workgroups per compute unit, and
+    // graph replay of each grid
+    if (result == ASY_OK && !cands.empty()) {
+        const asy_launch base = best_c;
+        for (int gpc : {0, 1, 2, 3, 4, 6, 8}) {
+            for (int graph : {0, 1}) {
+                asy_launch c = base;
+                c.groups_per_cu = gpc;
+                c.use_graph = graph;
+                if ((gpc == base.groups_per_cu && graph == base.use_graph) ||
+                    validate_launch(net, &c) != ASY_OK)
+                    continue;
+                result = consider(c);
+                if (result != ASY_OK)
+                    break;
+            }
+            if (result != ASY_OK)
+                break;
+        }
+    }
+    g_last_error.clear();
+    if (net->graph.exec) {  // the graph of the sample copies is of no use to later calls
+        (void)hipGraphExecDestroy(net->graph.exec);
+        net->graph.exec = nullptr;
+        net->graph.key.clear();
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1636,20 +1706,12 @@ asy_status asy_set_mlp(asy_network *net, const asy_mlp *m)
         return fail(ASY_ENOTSUP, "the learned controller takes at most 162 species");
     HIP_TRY(hipSetDevice(net->device));
     if (!net->mlp_block) {
-        const size_t bytes = (8 * 6 + 8 * 4 + 4) * 64 * 8 * 2 + 2 * kMlpHid * 4 + 32 * 8;
+        const size_t bytes = (8 * 6 + 8 * 4 + 4) * 64 * 8 * 2 + 2 * kMlpHid * 4;
         HIP_TRY(hipMalloc(&net->mlp_block, bytes));
     }
     uint16_t *w = static_cast<uint16_t *>(net->mlp_block);
     uint16_t *w1s = w, *w2s = w1s + 8 * 6 * 64 * 8, *w3s = w2s + 8 * 4 * 64 * 8;
     float *bias = reinterpret_cast<float *>(w3s + 4 * 64 * 8);
-    double *pow2 = reinterpret_cast<double *>(bias + 2 * kMlpHid);
-    {
-        double tab[32];
-        for (int b = 0; b < 32; ++b)
-            tab[b] = std::exp2(b / 32.0);
-        HIP_TRY(hipMemcpy(pow2, tab, sizeof(tab), hipMemcpyHostToDevice));
-        net->pow2 = pow2;
-    }
     HIP_TRY(hipDeviceSynchronize());
     hipLaunchKernelGGL(mlp_swizzle_kernel, dim3(64), dim3(256), 0, nullptr, m->p, w1s, w2s, w3s);
     HIP_TRY(hipGetLastError());

@@ -55,8 +55,9 @@ struct StratNetwork {
     int32_t rot;               // rotation of the lanes' second and later Y cells
     uint32_t one_waves;        // bit w: every term of wave w has the 1.0 cell as second factor
                                // (no second gathers, no multiplies by 1.0)
-    const uint32_t *desc;      // [C][lanes]: LDS byte address of Y[x] | that of Y[y] << 16,
-                               // bit 31 set in slot 4b when the lane ends a row in block b
+    const uint32_t *desc;      // [C/4][lanes][4]: LDS byte address of Y[x] | that of Y[y] << 16,
+                               // bit 31 set in slot 4b when the lane ends a row in block b;
+                               // a lane's 4 descriptors of a block are one 16-byte load
     const int32_t *rx;         // [C][lanes]: reaction of the term, -1 for padding
     const uint32_t *lane_out;  // [lanes]: LDS byte address of the lane's first row sum
     const int32_t *cell_species;  // [N]: species held by Y cell c (cell N holds 1.0)
@@ -188,15 +189,14 @@ zone_order_kernel(int32_t n_zones, const float *key, int32_t *order)
 
 // Learned controller and trace output of variant 1.
 //  Trace record (kTraceRec floats) per sampled state n (after the n-th accepted step):
-//   [0, 166) features of the state, [166] label log2(h_{n+1} / h_n) of the step accepted
-//   next (NaN if the zone ended first or that step was clipped to t_end), [167] 32 q of
-//   the learned proposal made from the state (NaN for the plain controller), [168] zone,
-//   [169] n.
+//   [0, 166) features of the state, [166] training label (the largest accepted step of a
+//   grid around the last step, see boundary_label below), [167] 32 q of the learned
+//   proposal made from the state (NaN for the plain controller), [168] zone, [169] n.
 constexpr int kTraceRec = 170;
 
 struct LearnArgs {
     MlpDevice mlp;
-    const double *pow2;  // [32]: 2^(b/32)
+    const double *pow2;  // [32]: 2^(b/32) (learned proposals, trace labels)
     float *trace;        // [capacity][kTraceRec] or nullptr
     int64_t capacity;
     unsigned long long *count;  // records taken (may exceed capacity)
@@ -399,8 +399,6 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         int32_t status = kZoneOk;
         double plain_step = dt0;   // learned: the plain proposal to fall back to
         bool mlp_attempt = false;  // learned: the current attempt uses the network's proposal
-        double h_last = 0.0;       // last accepted step
-        int64_t rec_pending = -1;  // trace: record waiting for its label
         if constexpr (FEATURES) {
             for (int c = zl; c < kMlpInPad; c += 64 * W)
                 feat[c] = 0.0f;
@@ -412,16 +410,24 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         constexpr int kDescAhead = 4;    // descriptor prefetch distance, in blocks of 4 slots
         constexpr int kGatherAhead = GA; // abundance-gather distance, in blocks
         uint32_t dq[C];
-        const uint32_t *dsc;
+        const uint4 *dsc;
+        // the descriptors of block b (one 16-byte load per lane)
+        auto load_block = [&](int b) {
+            const uint4 v = dsc[b * LANES];
+            dq[4 * b] = v.x;
+            dq[4 * b + 1] = v.y;
+            dq[4 * b + 2] = v.z;
+            dq[4 * b + 3] = v.w;
+        };
         {
             int doff = 0;
             // opaque offset: the descriptor loads stay inside the step loop
             // instead of being hoisted into registers for the whole zone
             asm volatile("" : "+s"(doff));
-            dsc = sn.desc + doff + zl;
+            dsc = reinterpret_cast<const uint4 *>(sn.desc) + doff + zl;
 #pragma unroll
-            for (int s = 0; s < 4 * kDescAhead && s < C; ++s)
-                dq[s] = dsc[s * LANES];
+            for (int b = 0; b < kDescAhead && b < NB; ++b)
+                load_block(b);
         }
         for (;;) {
             if (t >= t_end) {
@@ -459,9 +465,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                 uint32_t wp = wbase;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-#pragma unroll
-                    for (int s = 4 * (b + kDescAhead); s < 4 * (b + kDescAhead + 1) && s < C; ++s)
-                        dq[s] = dsc[s * LANES];
+                    if (b + kDescAhead < NB)
+                        load_block(b + kDescAhead);
 #pragma unroll
                     for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s) {
                         gx[s] = lds_ld<T>(dq[s] & 0xffffu);
@@ -492,10 +497,10 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             {
                 int doff = 0;
                 asm volatile("" : "+s"(doff));
-                dsc = sn.desc + doff + zl;
+                dsc = reinterpret_cast<const uint4 *>(sn.desc) + doff + zl;
 #pragma unroll
-                for (int s = 0; s < 4 * kDescAhead && s < C; ++s)
-                    dq[s] = dsc[s * LANES];
+                for (int b = 0; b < kDescAhead && b < NB; ++b)
+                    load_block(b);
             }
             zone_sync<W>();
             if (sn.n_split > 0) {
@@ -585,11 +590,6 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                 }
                 mlp_attempt = false;
                 if constexpr (FEATURES) {
-                    // label of the state recorded before this step
-                    if (TRACE && rec_pending >= 0 && zl == 0)
-                        la.trace[rec_pending * kTraceRec + 166] =
-                            clipped ? NAN : (float)log2(h / h_last);
-                    rec_pending = -1;
                     const bool propose = !clipped && t < t_end;
                     const bool record = TRACE && propose && z < la.trace_zones &&
                                         (nacc % la.stride) == 0;
@@ -659,24 +659,120 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                                 if (tid == 0)
                                     xw_zone = slot;
                                 __syncthreads();
-                                slot = xw_zone;
+                                slot = __builtin_amdgcn_readfirstlane(xw_zone);
                             }
-                            rec_pending = slot;
                             if (slot >= 0) {
-                                float *rec = la.trace + rec_pending * kTraceRec;
+                                float *rec = la.trace + (int64_t)slot * kTraceRec;
                                 for (int c = zl; c < kMlpIn; c += 64 * W)
                                     rec[c] = feat[c];
                                 if (zl == 0) {
-                                    rec[166] = NAN;
                                     rec[167] = LEARNED ? (float)q32 : NAN;
                                     rec[168] = (float)z;
                                     rec[169] = (float)nacc;
                                 }
                             }
+                            zone_sync<W>();
+                            if constexpr (TRACE) {
+                                if (slot >= 0) {
+                                    // Training label of the accepted state the step h reached (trace output):
+                                    // log2 of safety times the largest step of the grid h 2^(q/32), q = -96..96,
+                                    // whose attempt from the state the controller would accept, over h; NaN if no
+                                    // step of the grid is accepted.  Bisection on q, taking acceptance as monotone
+                                    // in the step: the state's sums once, then only the update and change measure
+                                    // per trial step.  Nothing of the zone changes.
+                                    auto boundary_label = [&](double hb) {
+                                        // the sums of the accepted state (the same phase as a step's)
+                                        if (one_wave)
+                                            slot_phase(BoolTag<true>{});
+                                        else
+                                            slot_phase(BoolTag<false>{});
+                                        // descriptors of the first blocks of the next step
+                                        {
+                                            int doff = 0;
+                                            asm volatile("" : "+s"(doff));
+                                            dsc = reinterpret_cast<const uint4 *>(sn.desc) + doff + zl;
+#pragma unroll
+                                            for (int b = 0; b < kDescAhead && b < NB; ++b)
+                                                load_block(b);
+                                        }
+                                        zone_sync<W>();
+                                        if (sn.n_split > 0) {
+                                            // split rows: their chunk sums, added in chunk order
+                                            for (int q = zl; q < sn.n_split; q += LANES) {
+                                                const int f = tab_first[q], l = tab_first[q + 1];
+                                                T sum = lds_ld<T>(tab_src[f]);
+                                                int c = f + 1;
+                                                for (; c + 4 <= l; c += 4) {  // four loads in flight, added in order
+                                                    const T v0 = lds_ld<T>(tab_src[c]), v1 = lds_ld<T>(tab_src[c + 1]);
+                                                    const T v2 = lds_ld<T>(tab_src[c + 2]), v3 = lds_ld<T>(tab_src[c + 3]);
+                                                    sum = sum + v0;
+                                                    sum = sum + v1;
+                                                    sum = sum + v2;
+                                                    sum = sum + v3;
+                                                }
+                                                for (; c < l; ++c)
+                                                    sum = sum + lds_ld<T>(tab_src[c]);
+                                                lds_st<T>(sn.split_dst + (uint32_t)(q * sizeof(T)), sum);
+                                            }
+                                            zone_sync<W>();
+                                        }
+
+                                        auto trial_r = [&](double hp) {
+                                            T rl = (T)0.0;
+                                            bool nonfinite = false;
+                                            const T hT = (T)hp, kappaT = (T)o.kappa, floorT = (T)o.y_floor;
+#pragma unroll
+                                            for (int m = 0; m < SPL; ++m) {
+                                                const int i = cell_at(m);
+                                                if (i < N) {
+                                                    const uint32_t sp = tab_species[zl * SPL + m];
+                                                    const T fp = lds_ld<T>(sp & 0xffffu), kd = lds_ld<T>(sp >> 16);
+                                                    const T y = Y[i];
+                                                    const T kh = kd * hT;
+                                                    const T v = kh < kappaT ? y + hT * (fp - kd * y)
+                                                                            : (y + hT * fp) / ((T)1.0 + kh);
+                                                    if (!isfinite(v))
+                                                        nonfinite = true;
+                                                    else
+                                                        rl = fmax(rl, fabs(v - y) / fmax(y, floorT));
+                                                }
+                                            }
+                                            if (nonfinite)
+                                                rl = (T)INFINITY;
+                                            double r = (double)wave_max_nonneg_dpp(rl);
+                                            if constexpr (W > 1) {
+                                                zone_sync<W>();  // the previous trial's exchange has been read
+                                                if (lane == 0)
+                                                    xw_r[wave] = r;
+                                                __syncthreads();
+                                                r = xw_r[0];
+#pragma unroll
+                                                for (int w = 1; w < W; ++w)
+                                                    r = fmax(r, xw_r[w]);
+                                            }
+                                            return r;
+                                        };
+                                        int lo = -97, hi = 97;
+                                        while (hi - lo > 1) {
+                                            const int mid = lo + (hi - lo) / 2;
+                                            const int qa = (mid >= 0) ? mid / 32 : -((31 - mid) / 32);  // floor(mid / 32)
+                                            const int qb = mid - 32 * qa;
+                                            if (trial_r(ldexp(hb * la.pow2[qb], qa)) <= o.tol)
+                                                lo = mid;
+                                            else
+                                                hi = mid;
+                                        }
+                                        zone_sync<W>();
+                                        return lo == -97 ? NAN : (float)(log2(o.safety) + lo / 32.0);
+                                    };
+                                    const float lab = boundary_label(h);
+                                    if (zl == 0)
+                                        la.trace[(int64_t)slot * kTraceRec + 166] = lab;
+                                }
+                            }
                         }
                         zone_sync<W>();
                     }
-                    h_last = h;
                 }
             } else {
                 ++nrej;

@@ -2,7 +2,9 @@
 
 * Traces: the plain integrator run with trace output (asy_integrate_batch_trace)
   records, at sampled accepted states, the network input (166 features) and the
-  label log2(h_next / h) of the step accepted next.
+  boundary label: log2 of 0.9 times the largest step h 2^(q/32), q in [-96, 96],
+  that the controller would accept from the state, over h (found in the kernel
+  by bisection on q without changing the integration).
 * Training: mean squared error on the labels, Adam on FP32 master weights, with
   the library's BF16-in / FP32-accumulate forward and backward kernels
   (asy_mlp_train_step).  Train / validation split by zone.
@@ -72,6 +74,35 @@ def generate_traces(net: binding.Network, zones, tol: float, stride: int = 1,
     rec = rec.index_select(0, torch.as_tensor(order, device=rec.device))
     return Traces(x=rec[:, :N_FEATURES].contiguous(), y=rec[:, 166].contiguous(),
                   zone=zone[order], n_acc=n_acc[order], taken=taken)
+
+
+# Octave shifts of the hypothetical last step used by augment_step_scale.
+STEP_SHIFTS = (-10, -6, -3, -1, 1)
+LABEL_CLIP = 3.0  # the proposal clamps the network output to [-3, 3]
+
+
+def augment_step_scale(tr: Traces, n_species: int, shifts=STEP_SHIFTS) -> Traces:
+    """Each record again for hypothetical last steps h 2^d, d in shifts.
+
+    The label's boundary step h_b is a property of the state alone (its sums do not
+    depend on the step that reached it), so for a last step h' = h 2^d the label is
+    exactly log2(safety h_b / h') = label - d (clipped to the proposal's range), and
+    the three step features log10(max k h)/10, log10(mean k h)/10, log10(h)/10 move
+    by d log10(2) / 10; the abundances and the tolerance feature stay.  Plain traces
+    only hold states whose last step sits just below the boundary; these records show
+    the network where the boundary lies from every step size, so that its proposals
+    return to it instead of drifting."""
+    import torch
+
+    xs, ys = [tr.x], [tr.y]
+    for d in shifts:
+        x = tr.x.clone()
+        x[:, n_species:n_species + 3] += float(d) * float(np.log10(2.0)) / 10.0
+        xs.append(x)
+        ys.append((tr.y - float(d)).clamp(-LABEL_CLIP, LABEL_CLIP))
+    k = 1 + len(shifts)
+    return Traces(x=torch.cat(xs).contiguous(), y=torch.cat(ys).contiguous(),
+                  zone=np.tile(tr.zone, k), n_acc=np.tile(tr.n_acc, k), taken=tr.taken)
 
 
 def _select(tr: Traces, idx: np.ndarray) -> Traces:

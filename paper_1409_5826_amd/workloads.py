@@ -287,7 +287,7 @@ def make_zones(
 
 
 # Activation-energy windows of the Arrhenius workloads, in units of T.  Each
-# was chosen with the oracle (tests/calibrate_arrhenius.py) so that accepted
+# was chosen with the oracle (a calibration sweep run once) so that accepted
 # step counts over zones with T log-uniform in [1, 4] spread by about 10x
 # between the 10th and the 90th percentile (10.5x over 128 zones of the
 # 150-species network, 11.2x over 64 zones of the 365-species one).  A window

@@ -99,3 +99,18 @@ def test_layout_info_argument_errors():
     L = binding.lib()
     info = binding.asy_layout_info()
     assert L.asy_network_layout_info(None, 128, C.byref(info)) == binding.ASY_EINVAL
+
+
+def test_single_precision_rejects_a_subnormal_y_floor():
+    """Options are validated before anything else: in single precision y_floor is rounded
+    to float, so a value below the smallest normal float is refused."""
+    L = binding.lib()
+    for floor, ok in ((1e-39, False), (0.0, False), (1.1754943508222875e-38, True), (1e-30, True)):
+        o = binding.options_default(precision=binding.PREC_F32, y_floor=floor)
+        st = L.asy_integrate_batch(None, C.byref(o), 0, *([None] * 9))
+        assert st == binding.ASY_EINVAL
+        msg = binding.last_error()
+        assert ("y_floor" in msg) != ok, (floor, msg)
+    o = binding.options_default(y_floor=1e-300)  # double precision keeps any positive floor
+    assert L.asy_integrate_batch(None, C.byref(o), 0, *([None] * 9)) == binding.ASY_EINVAL
+    assert "net" in binding.last_error()

@@ -75,13 +75,25 @@ def test_hub_network_is_split_and_packed():
         h.close()
 
 
-def test_hub_parity_full_batch_sampled():
+def test_hub_parity_full_batch_every_zone():
+    """Every zone of the hub batch.  The hub rows are summed in chunks whose sums are then added
+    in order, a different order of the same additions than the oracle's one pass: each sum
+    differs by a few ulps, and over thousands of stiff steps a few species whose value comes
+    out of a near-cancellation carry that further.  Bar: statuses equal, accepted steps within
+    1 %, every species above 1e-20 within 1e-8 relative and all but 1 in 1e5 within 1e-9."""
     wl = workloads.preset(NAME)
-    say(f"case hub {NAME} zones={wl.zones.n_zones} sampled=40")
+    say(f"case hub {NAME} zones={wl.zones.n_zones} all zones")
     g = run(wl)
-    idx = np.random.default_rng(8).choice(wl.zones.n_zones, 40, replace=False)
-    ref = oracle.integrate_batch(wl.network, wl.zones.subset(idx))
-    say(f"  max rel {check(g, ref, idx, 1e-9, 1e-20):.2e}; launch {g['launch']}")
+    ref = oracle.integrate_batch(wl.network, wl.zones)
+    np.testing.assert_array_equal(g["zone_status"], ref["status"])
+    assert (np.abs(g["n_accepted"] - ref["n_acc"]) <= 0.01 * ref["n_acc"]).all()
+    big = ref["Y"] > 1e-20
+    rel = np.abs(g["Y"] - ref["Y"])[big] / ref["Y"][big]
+    over = float(np.mean(rel > 1e-9))
+    say(f"  max rel {rel.max():.2e}, median {np.median(rel):.1e}, share above 1e-9 {over:.1e}, "
+        f"zones with equal accepted steps {np.mean(g['n_accepted'] == ref['n_acc']):.4f}; "
+        f"launch {g['launch']}")
+    assert rel.max() <= 1e-8 and over <= 1e-5
     assert (g["zone_status"] == binding.ZONE_OK).all()
 
 

@@ -1,14 +1,18 @@
 """GPU learned controller and trace records against the oracle.
 
-The learned controller changes only which trial step is proposed.  To check
-the integrator under it bit for bit, the proposals the GPU made (the 32 q it
-records with stride 1) are replayed in the oracle; on constant-rate networks
-the replayed trajectory must equal the GPU's exactly (Y, next dt, step counts,
-status), and the oracle's proposal log must equal the GPU's records (features
-and labels to float rounding of log10 / log2, accepted-step counts exactly).
-The q the GPU's in-kernel network produced are checked separately against the
-oracle network evaluated on the recorded features: equal except where 32 o
-lies within 0.02 of a rounding boundary (FP32 against FP64 accumulation).
+The learned controller changes only which trial step is proposed.  Its proposal
+q is an integer that floating point decides, so the oracle evaluates the network
+in the device's matrix-core arithmetic (oracle.mlp_forward_mfma: BF16 operands,
+FP32 accumulation by the rule measured on gfx950).  Checks:
+* every q the GPU recorded equals the oracle network's q on the recorded
+  features (all but a few in 10^4, the mismatch rate of the accumulation rule);
+* replaying the GPU's q in the oracle reproduces the trajectory exactly on
+  constant-rate networks and within the parity bar with Arrhenius rates, and the
+  oracle's proposal log equals the GPU's records (features to float rounding of
+  log10, boundary labels, accepted-step counts exactly);
+* end to end, with a network trained by the library's own pipeline, the oracle
+  running that network itself reproduces the GPU's accepted-step sequence in at
+  least 99 % of 128 zones of the 150-species constant-rate workload.
 """
 import sys
 
@@ -69,7 +73,7 @@ def zone_rates(wl, zones, i):
 
 
 def run(torch, wl, zones, learned, params=None, trace_cap=0, stride=1, trace_zones=None,
-        launch=None):
+        launch=None, max_steps=MAX_STEPS):
     net = binding.Network(wl.network)
     m = None
     try:
@@ -80,7 +84,7 @@ def run(torch, wl, zones, learned, params=None, trace_cap=0, stride=1, trace_zon
             m.set_params(params)
             net.set_mlp(m)
         opts = binding.options_default(controller=binding.CTRL_LEARNED if learned else
-                                       binding.CTRL_PLAIN, max_steps=MAX_STEPS)
+                                       binding.CTRL_PLAIN, max_steps=max_steps)
         buf = net.zone_buffers(zones)
         out = {}
         if trace_cap:
@@ -111,29 +115,33 @@ def records_by_zone(trace):
     return {int(k): t[zs == k] for k in np.unique(zs)}
 
 
-def check_log(rec, log, N):
-    """GPU records of one zone against the oracle's proposal log entries with the same n_acc."""
+def check_log(rec, log, N, label_mismatch_max=0.0):
+    """GPU records of one zone against the oracle's proposal log entries with the same n_acc.
+    With Arrhenius rates (last-bit differences of exp) a boundary label may sit on the other
+    side of a grid point: label_mismatch_max bounds the share of such records."""
     n = rec[:, 169].astype(np.int64)
     idx = np.searchsorted(log["n_acc"], n)
     assert (idx < len(log["n_acc"])).all() and (log["n_acc"][idx] == n).all()
     np.testing.assert_allclose(rec[:, :N + 4], log["feat"][idx, :N + 4], rtol=0, atol=FEAT_ATOL)
     assert (rec[:, N + 4:166] == 0).all()
     lab_g, lab_o = rec[:, 166].astype(np.float64), log["label"][idx]
-    np.testing.assert_array_equal(np.isnan(lab_g), np.isnan(lab_o))
-    ok = ~np.isnan(lab_o)
-    np.testing.assert_allclose(lab_g[ok], lab_o[ok], rtol=0, atol=LABEL_ATOL)
+    both = ~np.isnan(lab_g) & ~np.isnan(lab_o)
+    differ = (np.isnan(lab_g) != np.isnan(lab_o)) | (both & (np.abs(lab_g - lab_o) > LABEL_ATOL))
+    assert (differ.mean() if differ.size else 0.0) <= label_mismatch_max, \
+        f"{differ.sum()} labels differ"
 
 
-def check_q_against_network(params, trace, max_checks=1500):
+def check_q_against_network(params, trace, max_checks=3000):
+    """q of the GPU's in-kernel network against the oracle's matrix-core forward on the same
+    recorded features."""
     rng = np.random.default_rng(0)
     sel = rng.choice(len(trace), size=min(max_checks, len(trace)), replace=False)
-    o = np.array([oracle.mlp_forward_c(params, trace[i, :166]) for i in sel])
+    o = np.array([oracle.mlp_forward_mfma(params, trace[i, :166]) for i in sel])
     q_ref = np.rint(32.0 * np.clip(o, -3.0, 3.0))
     q_gpu = trace[sel, 167]
-    near = np.abs(np.abs(32.0 * np.clip(o, -3, 3) - np.floor(32.0 * np.clip(o, -3, 3))) - 0.5) < 0.02
-    bad = (q_gpu != q_ref) & ~near
-    assert not bad.any(), f"{bad.sum()} q differ from the oracle network"
-    assert np.mean(q_gpu == q_ref) > 0.95
+    frac = float(np.mean(q_gpu == q_ref))
+    say(f"  q equal to the oracle network's on {frac:.5f} of {len(sel)} records")
+    assert frac >= 0.999
     return len(np.unique(q_gpu))
 
 
@@ -181,7 +189,7 @@ def test_learned_integration_replays_in_oracle(torch_dev, name, n_zones, t_scale
             rel = np.abs(g["Y"][z] - o["Y"])[big] / o["Y"][big]
             assert rel.max(initial=0) <= 1e-9
             assert abs(g["n_accepted"][z] - o["n_acc"]) <= 0.01 * o["n_acc"]
-        check_log(rec, o["log"], N)
+        check_log(rec, o["log"], N, 0.0 if exact else 0.01)
     # the learned kernel without trace output takes the same steps
     g2 = run(torch, wl, zones, True, p)
     np.testing.assert_array_equal(g2["Y"], g["Y"])
@@ -212,7 +220,7 @@ def test_plain_trace_records_stride_and_zone_limit(torch_dev):
         o = oracle.integrate_zone_learned(wl.network, zones.k[z], zones.Y0[z], zones.t_end[z],
                                           zones.dt0[z], learned=False,
                                           opts=oracle.options(max_steps=MAX_STEPS),
-                                          log_capacity=10 ** 6)
+                                          log_capacity=10 ** 6, label_stride=3)
         np.testing.assert_array_equal(g["Y"][z], o["Y"])
         want = o["log"]["n_acc"][o["log"]["n_acc"] % 3 == 0]
         np.testing.assert_array_equal(by_zone[z][:, 169].astype(np.int64), want)
@@ -264,3 +272,66 @@ def test_learned_controller_argument_errors(torch_dev):
         torch.cuda.synchronize()
     finally:
         net.close()
+
+
+def test_learned_end_to_end_with_a_trained_network(torch_dev):
+    """Train the proposer with the library's own pipeline (plain traces with boundary labels on
+    64 training zones, augmented for other step sizes, BF16 MFMA training on the device), then
+    integrate 64 zones of the 150-species constant-rate workload with it on the GPU and in the
+    oracle, which evaluates the same parameters itself.  Bar: identical accepted-step sequences
+    (Y, next dt, accepted and rejected counts, status) in at least 99 % of the zones; the others
+    within 1 % in accepted steps and 1e-6 relative in every abundance above 1e-20."""
+    import time
+    from concurrent.futures import ThreadPoolExecutor, as_completed
+
+    from paper_1409_5826_amd import learned
+
+    torch = torch_dev
+    tr_wl = workloads.preset("n150_r1604_const", n_zones=64, seed_offset=2003)
+    wl = workloads.preset("n150_r1604_const", n_zones=64)
+    say(f"case learned end to end: train on 64 zones, evaluate {wl.zones.n_zones} zones")
+    net = binding.Network(wl.network)
+    try:
+        traces = learned.generate_traces(net, tr_wl.zones, 1e-2, stride=12, capacity=200000)
+        traces = learned.augment_step_scale(traces, wl.network.n_species)
+        tr_set, va_set = learned.split_by_zone(traces, 0.1, 4005)
+        res = learned.train(tr_set, va_set, epochs=4, batch=1024, lr=1e-3, seed=4005)
+        params = res.mlp.get_params()
+        res.mlp.close()
+    finally:
+        net.close()
+    say(f"  trained on {len(tr_set.zone)} pairs: val loss {res.val_loss[-1]:.3e} "
+        f"(mean predictor {res.baseline_val_loss:.3e})")
+    max_steps = 100_000
+    g = run(torch, wl, wl.zones, True, params, max_steps=max_steps)
+    say(f"  GPU: accepted {int(g['n_accepted'].sum())}, rejected {int(g['n_rejected'].sum())}, "
+        f"statuses {np.bincount(g['zone_status'], minlength=5)}")
+    t0 = time.perf_counter()
+
+    def one(z):
+        return z, oracle.integrate_zone_learned(wl.network, wl.zones.k[z], wl.zones.Y0[z],
+                                                wl.zones.t_end[z], wl.zones.dt0[z], params,
+                                                opts=oracle.options(max_steps=max_steps))
+    outs = {}
+    with ThreadPoolExecutor(max_workers=16) as pool:
+        futs = [pool.submit(one, z) for z in range(wl.zones.n_zones)]
+        for i, f in enumerate(as_completed(futs)):
+            z, o = f.result()
+            outs[z] = o
+            if i % 8 == 7:
+                say(f"  oracle zones done {i + 1} ({time.perf_counter() - t0:.0f} s)")
+    same = []
+    for z in range(wl.zones.n_zones):
+        o = outs[z]
+        eq = (np.array_equal(g["Y"][z], o["Y"]) and g["dt"][z] == o["dt"] and
+              (g["n_accepted"][z], g["n_rejected"][z], g["zone_status"][z]) ==
+              (o["n_acc"], o["n_rej"], o["status"]))
+        same.append(eq)
+        if not eq:
+            assert g["zone_status"][z] == o["status"]
+            assert abs(g["n_accepted"][z] - o["n_acc"]) <= 0.01 * o["n_acc"]
+            big = o["Y"] > 1e-20
+            assert (np.abs(g["Y"][z] - o["Y"])[big] / o["Y"][big]).max() <= 1e-6
+    frac = float(np.mean(same))
+    say(f"  identical zones {frac:.4f}; oracle {time.perf_counter() - t0:.1f} s")
+    assert frac >= 0.99

@@ -80,14 +80,13 @@ def test_n150_constant_rates_128_zones():
     assert exact == 1.0
 
 
-@pytest.mark.parametrize("name,n_check", [("n150_r1604_arrhenius", 40), ("n365_r4400_arrhenius", 16)])
-def test_arrhenius_full_size_sampled(name, n_check):
+@pytest.mark.parametrize("name", ["n150_r1604_arrhenius", "n365_r4400_arrhenius"])
+def test_arrhenius_full_size_every_zone(name):
     wl = workloads.preset(name)
-    say(f"case f32 {name} zones={wl.zones.n_zones} sampled={n_check}")
+    say(f"case f32 {name} zones={wl.zones.n_zones} all zones")
     g = run_gpu(wl)
-    idx = np.random.default_rng(5).choice(wl.zones.n_zones, n_check, replace=False)
-    ref = oracle.integrate_batch(wl.network, wl.zones.subset(idx), precision=1)
-    exact = compare(g, ref, idx)
+    ref = oracle.integrate_batch(wl.network, wl.zones, precision=1)
+    exact = compare(g, ref)
     say(f"  bit-exact zones {exact:.3f}")
     assert (g["zone_status"] == binding.ZONE_OK).all()
 
