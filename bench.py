@@ -282,6 +282,11 @@ def cpu_baseline_leg(wl, stride, repeats=3, one_core_stride=64):
     }
 
 
+def log(msg):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 SWEEP_COUNTS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 1536, 1537, 2048, 3072, 3073)
 
 LAUNCH_STUDY = (
@@ -367,9 +372,11 @@ def main(argv=None):
     lds_measured = {w: binding.asy_probe_lds_bandwidth(w) / 1e9 for w in (8, 16)}
     peak = max(LDS_PEAK_GBS, *lds_measured.values())
     launch = json.loads(args.launch) if args.launch else None
+    log(f"LDS probe {lds_measured}")
     wl, net, buf, (Y0, dt0, stream), main_run = run_workload(
         args.workload, args.steps, args.warmup, peak, launch=launch,
         autotune=not args.no_autotune, n_zones=args.zones)
+    log(f"{wl.name}: {main_run['time_to_t_end_ms']:.2f} ms, launch {main_run['launch']}")
     prof = profiled_counters(wl.name)
     n = wl.network
 
@@ -409,6 +416,7 @@ def main(argv=None):
     }
     if not args.no_sweep and args.workload == "n150_r1604_arrhenius":
         out["launch_study"] = launch_study(net, buf, Y0, dt0, stream)
+        log("launch study done")
     if not args.no_f32:
         out["f32"] = f32_leg(net, buf, Y0, dt0, stream, args.steps, b_step_fn=lambda: (
             algorithmic_bytes_per_zone_step(n.n_species, n.n_reactions, n.n_destruction, 4,
@@ -419,12 +427,16 @@ def main(argv=None):
                                          autotune=not args.no_autotune)
         net4.close()
         out["c4"] = c4
+        log(f"365 species: {c4['time_to_t_end_ms']:.2f} ms")
     if not args.no_sweep:
         out["zone_count_sweep"] = zone_count_sweep(args.workload, SWEEP_COUNTS)
+        log("zone-count sweep done")
     if not args.no_learned:
         out["learned"] = learned_leg(args.learned_zones)
+        log("learned leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_leg(wl, args.cpu_sample_stride)
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -521,20 +533,31 @@ def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3)) -> dict:
             parts.append(learned.subsample(tr, per_tol, 4005))
         pairs = learned.augment_step_scale(learned.concat(parts), ev.network.n_species)
         tr_set, va_set = learned.split_by_zone(pairs, 0.1, 4005)
+        log(f"learned: {len(pairs.zone)} training pairs")
         res = learned.train(tr_set, va_set, epochs=20, batch=1024, lr=1e-3, seed=4005)
+        log(f"learned: trained, val loss {res.val_loss[-1]:.3e}")
         net.set_mlp(res.mlp)
         rows, curves = [], {"plain": [], "learned": []}
         drift = None
         for tol in tols:
             row = {"tol": tol}
+            budget = None
             for form, is_learned in (("plain", False), ("learned", True)):
-                r = learned.integrate(net, ev.zones, tol, is_learned, repeats=1)
+                # the learned form gets 4x the plain form's largest attempt count per zone: a
+                # network that keeps shrinking the step ends there (status MAX_STEPS, counted)
+                r = learned.integrate(net, ev.zones, tol, is_learned, repeats=1,
+                                      max_steps=budget or 10_000_000)
+                if budget is None:
+                    budget = 4 * int((r.n_acc + r.n_rej).max())
                 err = learned.mass_error(r.Y[ref_idx], ref_Y, w)
                 row[form] = {"ms": r.ms, "accepted_per_zone": float(r.n_acc.mean()),
                              "rejected_per_zone": float(r.n_rej.mean()),
                              "err_max": float(err.max()), "err_median": float(np.median(err)),
-                             "zones_ok": int((r.status == binding.ZONE_OK).sum())}
+                             "zones_ok": int((r.status == binding.ZONE_OK).sum()),
+                             "max_steps": budget if is_learned else None}
                 curves[form].append((float(np.median(err)), r.ms))
+                log(f"learned: tol {tol:g} {form} {r.ms:.0f} ms, median error "
+                    f"{np.median(err):.3g}")
                 if form == "plain" and drift is None:
                     ratio = (r.Y @ w) / (ev.zones.Y0 @ w)
                     q = np.percentile(ratio, [10, 50, 90])

@@ -86,6 +86,8 @@ def lib():
         L = C.CDLL(_lib_path)
         P = C.c_void_p
         L.orc_rates_arrhenius.argtypes = [C.c_int32, P, P, C.c_double, P]
+        L.orc_exp_for_tests.argtypes = [C.c_double]
+        L.orc_exp_for_tests.restype = C.c_double
         L.orc_rhs.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P]
         L.orc_update.argtypes = [C.c_int32, P, P, P, C.c_double, C.c_double, P, P]
         L.orc_change.argtypes = [C.c_int32, P, P, C.c_double]
@@ -143,6 +145,11 @@ class _LearnLog(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("count", C.c_int64), ("q", C.c_void_p),
                 ("feat", C.c_void_p), ("label", C.c_void_p), ("n_acc", C.c_void_p),
                 ("label_stride", C.c_int64)]
+
+
+def exp_cw(x: float) -> float:
+    """The oracle's exponential of the Arrhenius factor (Cody-Waite reduction, Taylor degree 13)."""
+    return float(lib().orc_exp_for_tests(float(x)))
 
 
 def rates_arrhenius(A, E, T) -> np.ndarray:

@@ -46,12 +46,50 @@ typedef struct {
  * integration because temperature and density are frozen over a hydro step
  * (section "GPU Virtues and the Explicit Approach", its footnote on rates).
  */
+/*
+ * exp(x) for the Arrhenius factor, by a fixed algorithm that the device path
+ * evaluates the same way, so that both sides' rates agree bit for bit (the
+ * host and device libraries' exp differ in the last bit at times, and over
+ * thousands of steps such a difference can move an accept/reject decision):
+ * Cody and Waite's argument reduction x = n ln2 + r with n = rint(x / ln2) and
+ * ln2 split into LN2_HI (33 significant bits, so n LN2_HI is exact for
+ * |n| < 2^20) and LN2_LO, then the Taylor polynomial of exp(r) to degree 13
+ * (|r| <= ln2 / 2: truncation below 1e-17 relative) in Horner form with
+ * coefficients 1/k! (each one correctly rounded division), then 2^n exactly.
+ * Every operation rounds as written (no fused multiply-add).
+ */
+static double orc_exp(double x)
+{
+    static const double LN2_HI = 0x1.62e42fefp-1, LN2_LO = 0x1.473de6af278edp-34;
+    static const double INV_LN2 = 0x1.71547652b82fep+0;
+    if (isnan(x))
+        return x;
+    if (x > 709.782712893384)
+        return INFINITY;
+    if (x < -745.2)
+        return 0.0;
+    const double n = rint(x * INV_LN2);
+    const double r = (x - n * LN2_HI) - n * LN2_LO;
+    double fact = 1.0, c[14];
+    for (int k = 0; k <= 13; ++k) {
+        if (k > 0)
+            fact *= k; /* k! is exact in double up to 13! */
+        c[k] = 1.0 / fact;
+    }
+    double p = c[13];
+    for (int k = 12; k >= 0; --k)
+        p = p * r + c[k];
+    return ldexp(p, (int)n);
+}
+
 void orc_rates_arrhenius(int32_t n_reactions, const double *A, const double *E,
                          double T, double *k)
 {
     for (int32_t j = 0; j < n_reactions; ++j)
-        k[j] = A[j] * exp(-E[j] / T);
+        k[j] = A[j] * orc_exp(-E[j] / T);
 }
+
+double orc_exp_for_tests(double x) { return orc_exp(x); }
 
 /*
  * Creation flux F+_i and effective depletion rate k_i of Eq. (eq1.1):

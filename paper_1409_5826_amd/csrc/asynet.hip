@@ -112,20 +112,24 @@ using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *,
 
 // mode: 0 plain controller, 1 plain with trace, 2 learned, 3 learned with trace,
 //       4 plain controller in single precision
+// CR: slots whose rates the instance keeps in registers (the rest in LDS)
 struct StratInstance {
-    int W, SPL, C, mode;
+    int W, SPL, C, CR, mode;
     StratKernel fn;
 };
 
 #define ASY_STRAT(W_, SPL_, C_)                                                                 \
-    {W_, SPL_, C_, 0, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_>(), false, false>}
+    {W_, SPL_, C_, C_, 0, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_>(), false, false>}
+#define ASY_STRAT_CR(W_, SPL_, C_, CR_)                                                         \
+    {W_, SPL_, C_, CR_, 0, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<CR_>(), false,    \
+                                                false, double, CR_>}
 #define ASY_STRAT_F32(W_, SPL_, C_)                                                             \
-    {W_, SPL_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_, float>(), false,   \
-                                           false, float>}
+    {W_, SPL_, C_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_, float>(), false, \
+                                               false, float>}
 #define ASY_STRAT_LEARN(W_, SPL_, C_)                                                           \
-    {W_, SPL_, C_, 1, integrate_strat_kernel<W_, SPL_, C_, 2, false, true>},                    \
-    {W_, SPL_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                    \
-    {W_, SPL_, C_, 3, integrate_strat_kernel<W_, SPL_, C_, 2, true, true>}
+    {W_, SPL_, C_, C_, 1, integrate_strat_kernel<W_, SPL_, C_, 2, false, true>},                \
+    {W_, SPL_, C_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                \
+    {W_, SPL_, C_, C_, 3, integrate_strat_kernel<W_, SPL_, C_, 2, true, true>}
 const StratInstance kStratInstances[] = {
     ASY_STRAT(1, 1, 16), ASY_STRAT(1, 1, 32), ASY_STRAT(1, 2, 32), ASY_STRAT(1, 2, 48),
     ASY_STRAT(1, 3, 48), ASY_STRAT(1, 3, 64), ASY_STRAT(1, 3, 80), ASY_STRAT(1, 3, 96),
@@ -133,7 +137,7 @@ const StratInstance kStratInstances[] = {
     ASY_STRAT(2, 2, 48), ASY_STRAT(2, 2, 64), ASY_STRAT(2, 3, 64), ASY_STRAT(2, 3, 96),
     ASY_STRAT(2, 3, 104), ASY_STRAT(2, 3, 112),
     ASY_STRAT(4, 1, 16), ASY_STRAT(4, 1, 32), ASY_STRAT(4, 1, 40), ASY_STRAT(4, 1, 48),
-    ASY_STRAT(4, 2, 48), ASY_STRAT(4, 2, 56), ASY_STRAT(4, 2, 64), ASY_STRAT(4, 2, 80),
+    ASY_STRAT(4, 2, 48), ASY_STRAT_CR(4, 2, 56, 40), ASY_STRAT(4, 2, 64), ASY_STRAT(4, 2, 80),
     ASY_STRAT_LEARN(1, 1, 16), ASY_STRAT_LEARN(2, 2, 40), ASY_STRAT_LEARN(2, 2, 48),
     ASY_STRAT_F32(1, 1, 16), ASY_STRAT_F32(1, 1, 32), ASY_STRAT_F32(1, 2, 32), ASY_STRAT_F32(1, 2, 48),
     ASY_STRAT_F32(1, 3, 48), ASY_STRAT_F32(1, 3, 64), ASY_STRAT_F32(1, 3, 80), ASY_STRAT_F32(1, 3, 96),
@@ -144,6 +148,7 @@ const StratInstance kStratInstances[] = {
     ASY_STRAT_F32(4, 2, 48), ASY_STRAT_F32(4, 2, 56), ASY_STRAT_F32(4, 2, 64), ASY_STRAT_F32(4, 2, 80),
 };
 #undef ASY_STRAT
+#undef ASY_STRAT_CR
 #undef ASY_STRAT_F32
 #undef ASY_STRAT_LEARN
 
@@ -490,7 +495,11 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         sn.n_slots = C_needed;
         sn.xch = (n_cells * B + 255) / 256 * 256;
         sn.tab = sn.xch + kStratXchBytes;
-        sn.feat = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
+        // rates of the slots the plain instance does not keep in registers
+        const StratInstance *pi = find_strat_instance(W, L.SPL, L.C, p == 0 ? 0 : 4);
+        const int spill_slots = pi ? pi->C - pi->CR : 0;
+        sn.rlds = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
+        sn.feat = sn.rlds + spill_slots * lanes * B;
         sn.end_mask = end_mask;
         sn.one_waves = one_waves;
         // single precision: a lane's second and later Y cells start at the first one-factor wave

@@ -66,6 +66,45 @@ struct ZoneArgs {
     int32_t *queue;  // zone counter, zero at launch
 };
 
+// exp(x) of the Arrhenius factor k = A exp(-E/T), by a fixed algorithm (not the
+// device library's exp, whose last bit can differ from other implementations; over
+// thousands of steps such a difference can move an accept/reject decision):
+// Cody and Waite's reduction x = n ln2 + r, n = rint(x / ln2), with ln2 split into a
+// 33-bit head (n * head is exact for |n| < 2^20) and a tail; the Taylor polynomial of
+// exp(r) to degree 13 in Horner form, coefficients 1/k! (each a correctly rounded
+// division); then 2^n exactly.  Compiled without fused multiply-add.
+__host__ __device__ inline double rate_exp(double x)
+{
+    constexpr double kLn2Hi = 0x1.62e42fefp-1, kLn2Lo = 0x1.473de6af278edp-34;
+    constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+    if (isnan(x))
+        return x;
+    if (x > 709.782712893384)
+        return INFINITY;
+    if (x < -745.2)
+        return 0.0;
+    const double n = rint(x * kInvLn2);
+    const double r = (x - n * kLn2Hi) - n * kLn2Lo;
+    constexpr double f2 = 2.0, f3 = 6.0, f4 = 24.0, f5 = 120.0, f6 = 720.0, f7 = 5040.0,
+                     f8 = 40320.0, f9 = 362880.0, f10 = 3628800.0, f11 = 39916800.0,
+                     f12 = 479001600.0, f13 = 6227020800.0;
+    double p = 1.0 / f13;
+    p = p * r + 1.0 / f12;
+    p = p * r + 1.0 / f11;
+    p = p * r + 1.0 / f10;
+    p = p * r + 1.0 / f9;
+    p = p * r + 1.0 / f8;
+    p = p * r + 1.0 / f7;
+    p = p * r + 1.0 / f6;
+    p = p * r + 1.0 / f5;
+    p = p * r + 1.0 / f4;
+    p = p * r + 1.0 / f3;
+    p = p * r + 1.0 / f2;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)n);
+}
+
 __device__ inline double wave_max(double v)
 {
 #pragma unroll
@@ -240,7 +279,7 @@ integrate_group_kernel(DevNetwork net, DevOptions o, ZoneArgs za)
             else if (!(T > 0.0))
                 flag |= 2;
             for (int j = tid; j < R; j += NTHREADS) {
-                double kj = net.A[j] * exp(-net.E[j] / T);
+                double kj = net.A[j] * rate_exp(-net.E[j] / T);
                 k[j] = kj;
                 if (!isfinite(kj))
                     flag |= 1;

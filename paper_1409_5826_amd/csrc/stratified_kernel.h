@@ -50,6 +50,8 @@ struct StratNetwork {
     int32_t xch;               // LDS byte address of the exchange area (after the zone's cells)
     int32_t tab;               // LDS byte address of species_out (lane-major: the entry of
                                // the lane's m-th Y cell at zl * SPL + m), split_first, split_src
+    int32_t rlds;              // LDS byte address of the rates of slots >= CR (instances that
+                               // keep only CR slots' rates in registers): [C - CR][lanes] of T
     int32_t feat;              // LDS byte address of the learned controller's input and layers
     uint64_t end_mask;         // bit b: some lane ends a row in block b (slots 4b..4b+3)
     int32_t rot;               // rotation of the lanes' second and later Y cells
@@ -114,7 +116,7 @@ rates_arrhenius_kernel(int32_t n_zones, int32_t n_reactions, const double *A, co
         else if (!(Tz > 0.0))
             kj = -1.0;
         else
-            kj = A[j] * exp(-E[j] / Tz);
+            kj = A[j] * rate_exp(-E[j] / Tz);
         k[idx] = kj;
     }
 }
@@ -251,16 +253,20 @@ constexpr int strat_gather_ahead()
     return (sizeof(T) == 8 && C <= 40) ? 1 : 2;
 }
 
+// CR: the slots whose rates live in registers (the rest are read from LDS every step, one
+// conflict-free read per slot: lanes read consecutive cells), which lets a network that needs
+// many slots keep the register budget -- and occupancy -- of CR slots.
 template <int W, int SPL, int C, int GA = 2, bool LEARNED = false, bool TRACE = false,
-          typename T = double>
+          typename T = double, int CR = C>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
-                               amdgpu_waves_per_eu(strat_waves_per_eu<C, T>())))
+                               amdgpu_waves_per_eu(strat_waves_per_eu<CR, T>())))
 integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates,
                        const int32_t *order, LearnArgs la)
 {
     constexpr bool FEATURES = LEARNED || TRACE;
     static_assert(!FEATURES || sizeof(T) == 8, "learned controller and trace in double only");
     static_assert(C % 4 == 0, "slots come in blocks of 4");
+    static_assert(CR % 4 == 0 && CR <= C, "register-held rates cover whole blocks");
     static_assert(W <= 4, "the exchange area holds 4 waves");
     constexpr int LANES = 64 * W;
     extern __shared__ double lds[];
@@ -336,7 +342,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         int flag = 0;  // bit 0: non-finite input, bit 1: out-of-domain input
         // rates: gathered once per zone from the [zone][reaction] table (the
         // per-zone input, or the table the Arrhenius rate kernel filled)
-        T kr[C];
+        T kr[CR];
+        const uint32_t rl_lane = (uint32_t)sn.rlds + (uint32_t)zl * (uint32_t)sizeof(T);
         {
             const double *kz = rates + (size_t)z * R;
 #pragma unroll
@@ -350,7 +357,10 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                     else if (kj < 0.0)
                         flag |= 2;
                 }
-                kr[s] = (T)kj;
+                if (s < CR)
+                    kr[s] = (T)kj;
+                else
+                    lds_st<T>(rl_lane + (uint32_t)((s - CR) * LANES * (int)sizeof(T)), (T)kj);
             }
         }
         const double *Yz = za.Y + (size_t)z * N;
@@ -407,7 +417,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         // every term of this wave has the 1.0 cell as second factor (a uniform value)
         const bool one_wave = (sn.one_waves >> __builtin_amdgcn_readfirstlane(wave)) & 1u;
         constexpr int NB = C / 4;
-        constexpr int kDescAhead = 4;    // descriptor prefetch distance, in blocks of 4 slots
+        constexpr int kDescAhead = 3;    // descriptor prefetch distance, in blocks of 4 slots
         constexpr int kGatherAhead = GA; // abundance-gather distance, in blocks
         uint32_t dq[C];
         const uint4 *dsc;
@@ -454,13 +464,19 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             // the 1.0 cell, no second gathers and no products by 1.0 (exact)
             auto slot_phase = [&](auto one_tag) {
                 constexpr bool ONE = decltype(one_tag)::value;
-                T gx[C], gy[C];
-#pragma unroll
-                for (int s = 0; s < 4 * kGatherAhead && s < C; ++s) {
+                T gx[C], gy[C], kl[C];
+                // slot s's rate: a register, or (s >= CR) an LDS read issued with its gathers
+                auto rate_of = [&](int s) -> T { return s < CR ? kr[s < CR ? s : 0] : kl[s]; };
+                auto gather = [&](int s) {
                     gx[s] = lds_ld<T>(dq[s] & 0xffffu);
                     if constexpr (!ONE)
                         gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
-                }
+                    if (s >= CR)
+                        kl[s] = lds_ld<T>(rl_lane + (uint32_t)((s - CR) * LANES * (int)sizeof(T)));
+                };
+#pragma unroll
+                for (int s = 0; s < 4 * kGatherAhead && s < C; ++s)
+                    gather(s);
                 T acc = (T)0.0;
                 uint32_t wp = wbase;
 #pragma unroll
@@ -468,17 +484,14 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                     if (b + kDescAhead < NB)
                         load_block(b + kDescAhead);
 #pragma unroll
-                    for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s) {
-                        gx[s] = lds_ld<T>(dq[s] & 0xffffu);
-                        if constexpr (!ONE)
-                            gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
-                    }
+                    for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s)
+                        gather(s);
 #pragma unroll
                     for (int s = 4 * b; s < 4 * b + 4; ++s) {
                         if constexpr (ONE)  // second factor 1.0: the product by 1.0 is exact
-                            acc = acc + kr[s] * gx[s];
+                            acc = acc + rate_of(s) * gx[s];
                         else
-                            acc = acc + (kr[s] * gx[s]) * gy[s];
+                            acc = acc + (rate_of(s) * gx[s]) * gy[s];
                     }
                     if ((emask >> b) & 1u) {
                         if ((int32_t)dq[4 * b] < 0) {

@@ -1,8 +1,11 @@
-"""GPU MLP kernels (BF16 MFMA, FP32 accumulation) against the FP64 reference with
-BF16 rounding at the same points.  Tolerances: outputs 2e-3 absolute + 2e-3
-relative and gradients 3 % of each block's norm -- accumulation order differs
-(FP32 vs FP64), and an intermediate that lands next to a BF16 rounding boundary
-can round the other way."""
+"""GPU MLP kernels (BF16 MFMA, FP32 accumulation) against the reference network in the
+device's arithmetic (oracle.mlp forward_mfma / backward_mfma: the same BF16 rounding
+points, products accumulated by the matrix-core rule).  Bars: outputs equal in at
+least 99 % of the samples (a 1-ulp difference of the rule, or a hidden unit whose
+FP32 value then rounds to the other BF16, explains the rest; 3e-2 absolute at
+worst); gradients within 1e-3 of each parameter block's norm; the Adam update on the
+device's own gradient within 1e-4; three training steps within 2e-2 (Adam's
+per-element normalisation, see the test)."""
 import sys
 
 import numpy as np
@@ -61,12 +64,11 @@ def test_forward_and_infer_match_reference(torch_dev, n):
         torch.cuda.synchronize()
     finally:
         m.close()
-    o_ref, _ = ref.forward(p.astype(np.float64), x.astype(np.float64))
+    o_ref, _ = ref.forward_mfma(p.astype(np.float64), x.astype(np.float64))
     for o in (o_fwd, o_inf):
-        close = np.abs(o - o_ref) <= 2e-3 + 2e-3 * np.abs(o_ref)
-        # an intermediate within FP32-rounding distance of a BF16 rounding boundary may round the
-        # other way: one BF16 ulp (2^-8 relative) of one hidden unit, times its outgoing weights
-        assert close.mean() >= 0.99 and np.abs(o - o_ref).max() <= 3e-2
+        equal = o.astype(np.float64) == o_ref
+        say(f"  equal outputs {equal.mean():.4f}, max difference {np.abs(o - o_ref).max():.2e}")
+        assert equal.mean() >= 0.99 and np.abs(o - o_ref).max() <= 3e-2
 
 
 def exact_params_and_inputs(seed, n):
@@ -119,18 +121,69 @@ def test_gradient_matches_reference(torch_dev):
         loss, g = float(loss.cpu()[0]), g.cpu().numpy().astype(np.float64)
     finally:
         m.close()
-    l_ref, g_ref = ref.backward(p.astype(np.float64), x.astype(np.float64), y.astype(np.float64))
-    assert loss == pytest.approx(l_ref, rel=2e-3)
+    l_ref, g_ref = ref.backward_mfma(p.astype(np.float64), x.astype(np.float64),
+                                     y.astype(np.float64))
+    assert loss == pytest.approx(l_ref, rel=1e-5)
     off = 0
     for name, size in ref.SIZES.items():
         a, b = g[off:off + size], g_ref[off:off + size]
         off += size
-        assert np.linalg.norm(a - b) <= 0.03 * np.linalg.norm(b) + 1e-7, name
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        say(f"  {name}: relative difference {rel:.2e}")
+        assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b) + 1e-9, name
 
 
-def test_adam_steps_track_reference(torch_dev):
+def _blocks_close(step_gpu, step_ref, rel_tol, what):
+    off = 0
+    worst = 0.0
+    for name, size in ref.SIZES.items():
+        a, b = step_gpu[off:off + size], step_ref[off:off + size]
+        off += size
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        worst = max(worst, rel)
+        say(f"  {what} {name}: relative difference {rel:.2e}")
+        assert np.linalg.norm(a - b) <= rel_tol * np.linalg.norm(b) + 1e-9, name
+    return worst
+
+
+def test_adam_update_matches_reference_on_the_same_gradient(torch_dev):
+    """The Adam kernel alone: three steps, each checked against the reference update applied to
+    the gradient the device computed at the same parameters (FP32 moments and masters on both
+    sides), within 1e-4 of each block's norm."""
     torch = torch_dev
-    say("case mlp adam")
+    say("case mlp adam update")
+    p0 = params(5)
+    x, y = batch(6, 128)
+    m = binding.Mlp(128)
+    try:
+        m.set_params(p0)
+        xt, yt = torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda")
+        mm = np.zeros(ref.N_PARAMS)
+        vv = np.zeros(ref.N_PARAMS)
+        p = p0.astype(np.float64)
+        for t in range(1, 4):
+            _, g = m.gradient(xt, yt)
+            g = g.cpu().numpy().astype(np.float64)
+            m.train_step(xt, yt, lr=1e-3)
+            torch.cuda.synchronize()
+            p_gpu = m.get_params().astype(np.float64)
+            p_ref, mm, vv = ref.adam_step(p, g, mm, vv, t)
+            mm = mm.astype(np.float32).astype(np.float64)
+            vv = vv.astype(np.float32).astype(np.float64)
+            _blocks_close(p_gpu - p, p_ref - p, 1e-4, f"step {t}")
+            p = p_gpu
+    finally:
+        m.close()
+
+
+def test_adam_trajectory_tracks_reference(torch_dev):
+    """Three training steps on the device against three reference steps (gradients in the
+    matrix cores' arithmetic).  Adam divides each moment by its own magnitude, so a gradient
+    element near zero whose sign changes (one hidden gradient rounding to the other BF16 in a
+    few in 10^3 products) moves that element's step by up to 2 lr: measured 5.4e-3 of the W1
+    block's norm, all other blocks below 1e-6.  Bar 2e-2 per block."""
+    torch = torch_dev
+    say("case mlp adam trajectory")
     p0 = params(5)
     x, y = batch(6, 128)
     m = binding.Mlp(128)
@@ -147,11 +200,11 @@ def test_adam_steps_track_reference(torch_dev):
     mm = np.zeros_like(p)
     vv = np.zeros_like(p)
     for t in range(1, 4):
-        _, g = ref.backward(p, x.astype(np.float64), y.astype(np.float64))
+        # the device updates FP32 masters: the reference rounds its parameters the same way
+        _, g = ref.backward_mfma(p, x.astype(np.float64), y.astype(np.float64))
         p, mm, vv = ref.adam_step(p, g, mm, vv, t)
-    step_ref = p - p0
-    step_gpu = p_gpu - p0
-    assert np.linalg.norm(step_gpu - step_ref) <= 0.05 * np.linalg.norm(step_ref)
+        p = p.astype(np.float32).astype(np.float64)
+    _blocks_close(p_gpu - p0, p - p0, 2e-2, "trajectory")
 
 
 def test_training_reduces_loss(torch_dev):

@@ -301,3 +301,43 @@ def test_mfma_forward_agrees_with_the_fp64_reference():
     o32 = np.array([oracle.mlp_forward_mfma(p, xi) for xi in x])
     assert np.abs(o64).max() > 0.1
     np.testing.assert_allclose(o32, o64, rtol=0, atol=5e-3)
+
+
+def test_numpy_and_c_matrix_core_rule_agree():
+    """Two implementations of the accumulation rule (numpy mfma_matmul, C orc_mfma_dot) give the
+    same FP32 results on random bfloat16 data, and the numpy forward equals the C forward."""
+    import oracle
+
+    rng = np.random.default_rng(21)
+    A = mlp.bf16(rng.normal(size=(6, 64)) * 2.0 ** rng.integers(-6, 6, size=(6, 64)))
+    B = mlp.bf16(rng.normal(scale=0.1, size=(64, 5)))
+    got = mlp.mfma_matmul(A, B)
+    want = np.array([[oracle.mfma_dot(0.0, A[i], B[:, j]) for j in range(5)] for i in range(6)])
+    np.testing.assert_array_equal(got, want)
+    p = mlp.init_params(9)
+    u = mlp.unpack(p)
+    u["b1"] = rng.normal(scale=0.1, size=128)
+    u["b2"] = rng.normal(scale=0.1, size=128)
+    u["W3"] = rng.normal(scale=0.2, size=128)
+    p = mlp.pack(u).astype(np.float32)
+    x = rng.uniform(-1, 0, size=(8, mlp.N_IN)).astype(np.float32)
+    o, _ = mlp.forward_mfma(p.astype(np.float64), x)
+    o_c = np.array([oracle.mlp_forward_mfma(p, xi) for xi in x])
+    np.testing.assert_array_equal(o.astype(np.float32), o_c.astype(np.float32))
+
+
+def test_matrix_core_backward_close_to_fp64_backward():
+    """The backward pass in the device's arithmetic stays within FP32-accumulation distance of
+    the FP64 one (the rounding points are the same)."""
+    rng = np.random.default_rng(22)
+    p = mlp.init_params(3)
+    x = rng.uniform(-1, 0, size=(64, mlp.N_IN))
+    y = rng.normal(scale=0.3, size=64)
+    l64, g64 = mlp.backward(p, x, y)
+    l32, g32 = mlp.backward_mfma(p, x, y)
+    assert l32 == pytest.approx(l64, rel=1e-4)
+    off = 0
+    for name, n in mlp.SIZES.items():
+        a, b = g32[off:off + n], g64[off:off + n]
+        assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-9, name
+        off += n

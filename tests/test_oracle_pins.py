@@ -404,3 +404,21 @@ def test_zone_statuses():
     assert out["status"] == oracle.ZONE_BAD_INPUT
     out = oracle.integrate_zone(net, k, Y0, 0.0, 1e-12)
     assert out["status"] == oracle.ZONE_OK and out["n_acc"] == 0 and out["dt"] == 1e-12
+
+
+def test_rate_exponential_within_one_ulp_of_the_library():
+    """The oracle's exponential of the Arrhenius factor (a fixed algorithm both sides evaluate)
+    is the exponential to within one ulp over the whole finite range, exact at 0, e to one ulp
+    at 1, and overflows, underflows and propagates NaN like the exponential."""
+    import math
+
+    xs = np.concatenate([np.linspace(-745.0, 709.0, 4001), -np.linspace(6.0, 91.0, 4001)])
+    ref = np.exp(xs)
+    got = np.array([oracle.exp_cw(x) for x in xs])
+    ok = ref > 1e-300
+    ulps = np.abs(got[ok] - ref[ok]) / np.spacing(ref[ok])
+    assert ulps.max() <= 1.0 and np.mean(got[ok] == ref[ok]) > 0.8
+    assert oracle.exp_cw(0.0) == 1.0
+    assert abs(oracle.exp_cw(1.0) - math.e) <= np.spacing(math.e)
+    assert oracle.exp_cw(800.0) == math.inf and oracle.exp_cw(-800.0) == 0.0
+    assert math.isnan(oracle.exp_cw(math.nan))
