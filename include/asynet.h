@@ -203,6 +203,30 @@ asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_
                                const double *t_end, double *dt, int64_t *n_accepted,
                                int64_t *n_rejected, int32_t *zone_status, void *stream);
 
+/*
+ * asy_integrate_batch_noalloc: asy_integrate_batch for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * asy_integrate_batch, bit for bit, except:
+ *  - n_zones must not exceed 262144, nor, for an Arrhenius network, 65011456 /
+ *    (8 n_reactions) (5066 zones at 1604 reactions); ASY_EINVAL otherwise,
+ *    nothing queued;
+ *  - the call allocates nothing: its scratch (the zone counter; with zone_order
+ *    1 the scheduling keys and order; for Arrhenius networks the table of the
+ *    call's rates) is a 64 MiB static device array that every device the
+ *    library runs on holds until the process ends; the counter is cleared by a
+ *    kernel at the start of each call, keys, order and rates are rewritten for
+ *    every zone of the call;
+ *  - the launch configuration's graph replay is not used.
+ * All calls on one device share that device's array: calls that overlap in
+ * time on one device (several streams or threads, any handles) race and
+ * give wrong results.  Order them on one stream.
+ */
+asy_status asy_integrate_batch_noalloc(asy_network *net, const asy_options *opts, int32_t n_zones,
+                                       double *Y, const double *T, const double *k_zone,
+                                       const double *t_end, double *dt, int64_t *n_accepted,
+                                       int64_t *n_rejected, int32_t *zone_status, void *stream);
+
 /* Current launch configuration of a handle.  cfg: host, out. */
 asy_status asy_get_launch(const asy_network *net, asy_launch *cfg);
 

@@ -29,6 +29,7 @@ EXPORTS = (
     "asy_network_create",
     "asy_network_destroy",
     "asy_integrate_batch",
+    "asy_integrate_batch_noalloc",
     "asy_get_launch",
     "asy_set_launch",
     "asy_autotune",
@@ -139,6 +140,9 @@ def lib():
         L.asy_network_destroy.restype = None
         L.asy_integrate_batch.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, P, P, P, P]
         L.asy_integrate_batch.restype = I32
+        L.asy_integrate_batch_noalloc.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, P,
+                                                  P, P, P]
+        L.asy_integrate_batch_noalloc.restype = I32
         L.asy_get_launch.argtypes = [P, C.POINTER(asy_launch)]
         L.asy_get_launch.restype = I32
         L.asy_network_layout_info.argtypes = [P, I32, C.POINTER(asy_layout_info)]
@@ -248,10 +252,15 @@ def _stream_ptr(stream):
     return stream.cuda_stream
 
 
+NOALLOC_MAX_ZONES = 1 << 18
+NOALLOC_RATE_BYTES = 65011456  # rate-table part of the no-alloc scratch (Arrhenius networks)
+
+
 def asy_integrate_batch(handle, n_species, n_reactions, Y, t_end, dt, n_accepted, n_rejected,
                         zone_status, T=None, k_zone=None, opts: Optional[asy_options] = None,
-                        stream=None):
-    """Queue the integration of Y.shape[0] zones on `stream` (default: torch's current)."""
+                        stream=None, noalloc: bool = False):
+    """Queue the integration of Y.shape[0] zones on `stream` (default: torch's current).
+    noalloc=True calls asy_integrate_batch_noalloc (static device scratch, no allocation)."""
     import torch
 
     Z = int(Y.shape[0])
@@ -265,9 +274,9 @@ def asy_integrate_batch(handle, n_species, n_reactions, Y, t_end, dt, n_accepted
         _dev_ptr(n_rejected, torch.int64, (Z,), "n_rejected"),
         _dev_ptr(zone_status, torch.int32, (Z,), "zone_status"),
     ]
-    st = lib().asy_integrate_batch(handle, None if opts is None else C.byref(opts), Z, *args,
-                                   _stream_ptr(stream))
-    _check(st, "asy_integrate_batch")
+    fn = lib().asy_integrate_batch_noalloc if noalloc else lib().asy_integrate_batch
+    st = fn(handle, None if opts is None else C.byref(opts), Z, *args, _stream_ptr(stream))
+    _check(st, "asy_integrate_batch_noalloc" if noalloc else "asy_integrate_batch")
 
 
 def asy_integrate_batch_trace(handle, n_species, n_reactions, Y, t_end, dt, n_accepted, n_rejected,
@@ -405,10 +414,11 @@ class Network:
         )
         return buf
 
-    def integrate(self, buf, opts=None, stream=None):
+    def integrate(self, buf, opts=None, stream=None, noalloc=False):
         asy_integrate_batch(self.handle, self.n_species, self.n_reactions, buf["Y"], buf["t_end"],
                             buf["dt"], buf["n_accepted"], buf["n_rejected"], buf["zone_status"],
-                            T=buf["T"], k_zone=buf["k_zone"], opts=opts, stream=stream)
+                            T=buf["T"], k_zone=buf["k_zone"], opts=opts, stream=stream,
+                            noalloc=noalloc)
 
     def integrate_trace(self, buf, trace, count, stride=1, trace_zones=None, opts=None,
                         stream=None):

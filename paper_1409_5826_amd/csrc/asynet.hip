@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -57,7 +58,26 @@ struct GraphCache {
     std::vector<uint8_t> key;
 };
 
+// Scratch of asy_integrate_batch_noalloc, one copy per device for the life of
+// the process (64 MiB): the zone counter (256 B), the scheduling keys and order
+// of at most kNoAllocMaxZones zones, then the Arrhenius rate table [zones]
+// [reactions] (FP64), which bounds the zones of an Arrhenius network's call to
+// kScratchRateBytes / (8 n_reactions).  Host code never touches the array by
+// name (the name is a host-side stand-in); it uses the device address resolved
+// by scratch_setup.
+constexpr int32_t kNoAllocMaxZones = 1 << 18;
+constexpr size_t kScratchKeyOff = 256;
+constexpr size_t kScratchOrderOff = kScratchKeyOff + sizeof(float) * (size_t)kNoAllocMaxZones;
+constexpr size_t kScratchRateOff = kScratchOrderOff + sizeof(int32_t) * (size_t)kNoAllocMaxZones;
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr size_t kScratchRateBytes = kScratchBytes - kScratchRateOff;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` on each device
+
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct asy_network {
     int32_t n_species = 0;
@@ -578,6 +598,26 @@ hipError_t launch_variant0(asy_network *net, const DevOptions &o, const ZoneArgs
     return hipGetLastError();
 }
 
+// Resolve the device address of `scratch` on device dev, which must be
+// current; once per device (later calls return the cached address).
+asy_status scratch_setup(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(ASY_ENOTSUP, "device index beyond the scratch table");
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ASY_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                         hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    if (out)
+        *out = g_scratch_ptr[dev];
+    return ASY_OK;
+}
+
 // Per-call device scratch: the Arrhenius rates [zones][reactions] of variant 1,
 // the scheduling keys and the longest-first order [zones] (the zone counter
 // travels in ZoneArgs::queue).
@@ -1049,6 +1089,8 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
 
     if (check_strat_lds_base() != ASY_OK)
         return ASY_EDEVICE;
+    if (scratch_setup(dev, nullptr) != ASY_OK)  // device dev is current here
+        return ASY_EDEVICE;
 
     auto *net = new asy_network();
     net->n_species = N;
@@ -1267,10 +1309,23 @@ asy_status resolve_mode(const asy_network *net, const asy_options &o, bool trace
     return ASY_OK;
 }
 
+// Most zones asy_integrate_batch_noalloc takes on this network (-1 before a network exists):
+// the keys and order hold kNoAllocMaxZones, the rate table (Arrhenius networks)
+// kScratchRateBytes / (8 n_reactions).
+int64_t noalloc_max_zones(const asy_network *net)
+{
+    if (!net)
+        return -1;
+    int64_t limit = kNoAllocMaxZones;
+    if (net->rate_form == ASY_RATES_ARRHENIUS)
+        limit = std::min<int64_t>(limit, (int64_t)(kScratchRateBytes / (8 * (size_t)net->n_reactions)));
+    return limit;
+}
+
 asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n_zones, double *Y,
                             const double *T, const double *k_zone, const double *t_end, double *dt,
                             int64_t *n_accepted, int64_t *n_rejected, int32_t *zone_status,
-                            void *stream, bool trace, LearnArgs la)
+                            void *stream, bool trace, LearnArgs la, bool noalloc = false)
 {
     g_last_error.clear();
     asy_options o;
@@ -1284,6 +1339,12 @@ asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n
         return fail(ASY_EINVAL, "net must be non-NULL");
     if (n_zones < 0)
         return fail(ASY_EINVAL, "n_zones must be >= 0");
+    if (noalloc) {
+        const int64_t limit = noalloc_max_zones(net);
+        if (limit >= 0 && n_zones > limit)
+            return fail(ASY_EINVAL, "asy_integrate_batch_noalloc takes at most " +
+                                        std::to_string(limit) + " zones for this network");
+    }
     if (trace && (!la.trace || !la.count || la.capacity < 0 || la.capacity > INT32_MAX ||
                   la.stride < 1 || la.trace_zones < 0))
         return fail(ASY_EINVAL, "trace needs buffers, 0 <= capacity < 2^31, stride >= 1, "
@@ -1305,6 +1366,21 @@ asy_status integrate_common(asy_network *net, const asy_options *opts, int32_t n
     ZoneArgs za{n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected, zone_status, net->queue};
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(net->device));
+    if (noalloc) {
+        // the counter, keys and order in this device's static scratch; no graph (instantiating
+        // one allocates).  The counter is cleared by a kernel at the start of the launch; keys
+        // and order are rewritten for every zone of the call.
+        char *sp = nullptr;
+        st = scratch_setup(net->device, &sp);
+        if (st != ASY_OK)
+            return st;
+        za.queue = reinterpret_cast<int32_t *>(sp);
+        const CallBufs cb{reinterpret_cast<double *>(sp + kScratchRateOff),
+                          reinterpret_cast<float *>(sp + kScratchKeyOff),
+                          reinterpret_cast<int32_t *>(sp + kScratchOrderOff)};
+        HIP_TRY(launch_all(net, net->launch, to_dev(o), za, cb, s, mode, la));
+        return ASY_OK;
+    }
     st = ensure_call_bufs(net, net->launch, n_zones, s);
     if (st != ASY_OK)
         return st;
@@ -1320,6 +1396,15 @@ asy_status asy_integrate_batch(asy_network *net, const asy_options *opts, int32_
 {
     return integrate_common(net, opts, n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected,
                             zone_status, stream, false, LearnArgs{});
+}
+
+asy_status asy_integrate_batch_noalloc(asy_network *net, const asy_options *opts, int32_t n_zones,
+                                       double *Y, const double *T, const double *k_zone,
+                                       const double *t_end, double *dt, int64_t *n_accepted,
+                                       int64_t *n_rejected, int32_t *zone_status, void *stream)
+{
+    return integrate_common(net, opts, n_zones, Y, T, k_zone, t_end, dt, n_accepted, n_rejected,
+                            zone_status, stream, false, LearnArgs{}, true);
 }
 
 asy_status asy_integrate_batch_trace(asy_network *net, const asy_options *opts, int32_t n_zones,
