@@ -34,13 +34,15 @@ class Options(C.Structure):
         ("shrink_min", C.c_double),
         ("dt_min", C.c_double),
         ("max_steps", C.c_int64),
+        ("split_above", C.c_int32),
     ]
 
 
 def options(**kw) -> Options:
-    """Controller settings; defaults are the readings of the unspecified controller."""
+    """Controller settings; defaults are the readings of the unspecified controller.
+    split_above > 0 sums rows of more terms in chunks (see rhs); 0 sums every row in one pass."""
     d = dict(kappa=1.0, tol=0.01, y_floor=1e-10, grow_max=2.0, safety=0.9,
-             shrink_min=0.1, dt_min=1e-20, max_steps=10_000_000)
+             shrink_min=0.1, dt_min=1e-20, max_steps=10_000_000, split_above=0)
     d.update(kw)
     return Options(**d)
 
@@ -89,6 +91,8 @@ def lib():
         L.orc_exp_for_tests.argtypes = [C.c_double]
         L.orc_exp_for_tests.restype = C.c_double
         L.orc_rhs.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P]
+        L.orc_rhs_rows.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_int32, P, P]
+        L.orc_rhs_rows_f32.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, C.c_int32, P, P]
         L.orc_update.argtypes = [C.c_int32, P, P, P, C.c_double, C.c_double, P, P]
         L.orc_change.argtypes = [C.c_int32, P, P, C.c_double]
         L.orc_change.restype = C.c_double
@@ -159,13 +163,19 @@ def rates_arrhenius(A, E, T) -> np.ndarray:
     return k
 
 
-def rhs(net, k, Y):
-    """(F+, k_depletion) of Eq. eq1.1 at state Y."""
+def rhs(net, k, Y, split_above: int = 0):
+    """(F+, k_depletion) of Eq. eq1.1 at state Y.  split_above > 0: rows (the F+ or the k of
+    one species) of more terms are summed in chunks of split_above / 2 terms (rounded down to a
+    multiple of 4), whose sums are then added in order; otherwise every row in one pass."""
     a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
     k, Y = _f64(k), _f64(Y)
     n = net.n_species
     Fp, kd = np.empty(n), np.empty(n)
-    lib().orc_rhs(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), _p(Fp), _p(kd))
+    if split_above > 0:
+        lib().orc_rhs_rows(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), int(split_above),
+                           _p(Fp), _p(kd))
+    else:
+        lib().orc_rhs(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), _p(Fp), _p(kd))
     return Fp, kd
 
 
@@ -210,13 +220,17 @@ def integrate_zone(net, k, Y0, t_end, dt0, opts: Optional[Options] = None, trace
     return out
 
 
-def rhs_f32(net, k, Y):
-    """(F+, k_depletion) in float (inputs rounded to float first)."""
+def rhs_f32(net, k, Y, split_above: int = 0):
+    """(F+, k_depletion) in float (inputs rounded to float first); split_above as in rhs."""
     a, b, c = _i32(net.reactant0), _i32(net.reactant1), _i32(net.product)
     k, Y = np.ascontiguousarray(k, np.float32), np.ascontiguousarray(Y, np.float32)
     n = net.n_species
     Fp, kd = np.empty(n, np.float32), np.empty(n, np.float32)
-    lib().orc_rhs_f32(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), _p(Fp), _p(kd))
+    if split_above > 0:
+        lib().orc_rhs_rows_f32(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), int(split_above),
+                               _p(Fp), _p(kd))
+    else:
+        lib().orc_rhs_f32(n, len(a), _p(a), _p(b), _p(c), _p(k), _p(Y), _p(Fp), _p(kd))
     return Fp, kd
 
 

@@ -38,6 +38,7 @@ typedef struct {
     double shrink_min; /* smallest shrink factor of dt after a rejected step */
     double dt_min;     /* a rejection that asks for a smaller dt ends the zone */
     int64_t max_steps; /* attempted-step budget per zone */
+    int32_t split_above; /* rows with more terms are summed in chunks (orc_rhs_rows); 0: one pass */
 } orc_options;
 
 /*
@@ -121,6 +122,90 @@ void orc_rhs(int32_t n_species, int32_t n_reactions, const int32_t *a, const int
         }
         Fp[c[j]] += f;
     }
+}
+
+/*
+ * The sums of orc_rhs in another order of the same additions (reading: hub
+ * species, whose rows are far longer than the others, are summed in pieces).
+ * A row -- the F+ or the k of one species -- with more than split_above terms
+ * is cut into chunks of `chunk` consecutive terms in ascending reaction index,
+ * chunk = split_above / 2 rounded down to a multiple of 4 (at least 4); each
+ * chunk is summed from +0.0, and the chunk sums are added in chunk order, the
+ * first chunk's sum being the starting value.  Rows of at most split_above
+ * terms, and every row when split_above <= 0, are summed as in orc_rhs.
+ */
+static int32_t orc_chunk_terms(int32_t split_above)
+{
+    const int32_t chunk = split_above / 2 / 4 * 4;
+    return chunk < 4 ? 4 : chunk;
+}
+
+static double orc_row_sum(const double *t, int32_t n, int32_t split_above)
+{
+    if (split_above <= 0 || n <= split_above) {
+        double s = 0.0;
+        for (int32_t q = 0; q < n; ++q)
+            s += t[q];
+        return s;
+    }
+    const int32_t chunk = orc_chunk_terms(split_above);
+    double total = 0.0;
+    for (int32_t first = 0; first < n; first += chunk) {
+        double s = 0.0;
+        for (int32_t q = first; q < n && q < first + chunk; ++q)
+            s += t[q];
+        total = first == 0 ? s : total + s;
+    }
+    return total;
+}
+
+void orc_rhs_rows(int32_t n_species, int32_t n_reactions, const int32_t *a, const int32_t *b,
+                  const int32_t *c, const double *k, const double *Y, int32_t split_above,
+                  double *Fp, double *kd)
+{
+    if (split_above <= 0) {
+        orc_rhs(n_species, n_reactions, a, b, c, k, Y, Fp, kd);
+        return;
+    }
+    /* the terms of every row, in ascending reaction index */
+    int32_t *nF = calloc((size_t)n_species, sizeof(int32_t));
+    int32_t *nK = calloc((size_t)n_species, sizeof(int32_t));
+    int32_t *oF = malloc(sizeof(int32_t) * (size_t)(n_species + 1));
+    int32_t *oK = malloc(sizeof(int32_t) * (size_t)(n_species + 1));
+    double *tF = malloc(sizeof(double) * (size_t)(n_reactions + 1));
+    double *tK = malloc(sizeof(double) * (size_t)(2 * n_reactions + 1));
+    for (int32_t j = 0; j < n_reactions; ++j) {
+        nF[c[j]]++;
+        nK[a[j]]++;
+        if (b[j] >= 0)
+            nK[b[j]]++;
+    }
+    oF[0] = oK[0] = 0;
+    for (int32_t i = 0; i < n_species; ++i) {
+        oF[i + 1] = oF[i] + nF[i];
+        oK[i + 1] = oK[i] + nK[i];
+        nF[i] = nK[i] = 0;
+    }
+    for (int32_t j = 0; j < n_reactions; ++j) {
+        if (b[j] < 0) {
+            tF[oF[c[j]] + nF[c[j]]++] = k[j] * Y[a[j]];
+            tK[oK[a[j]] + nK[a[j]]++] = k[j];
+        } else {
+            tF[oF[c[j]] + nF[c[j]]++] = (k[j] * Y[a[j]]) * Y[b[j]];
+            tK[oK[a[j]] + nK[a[j]]++] = k[j] * Y[b[j]];
+            tK[oK[b[j]] + nK[b[j]]++] = k[j] * Y[a[j]];
+        }
+    }
+    for (int32_t i = 0; i < n_species; ++i) {
+        Fp[i] = orc_row_sum(tF + oF[i], nF[i], split_above);
+        kd[i] = orc_row_sum(tK + oK[i], nK[i], split_above);
+    }
+    free(nF);
+    free(nK);
+    free(oF);
+    free(oK);
+    free(tF);
+    free(tK);
 }
 
 /*
@@ -220,7 +305,7 @@ int32_t orc_integrate_zone(int32_t n_species, int32_t n_reactions, const int32_t
         /* reading: the last step is clipped to land exactly on t_end */
         int clipped = step >= t_end - t;
         double h = clipped ? t_end - t : step;
-        orc_rhs(n_species, n_reactions, a, b, c, k, Y, Fp, kd);
+        orc_rhs_rows(n_species, n_reactions, a, b, c, k, Y, o->split_above, Fp, kd);
         orc_update(n_species, Y, Fp, kd, h, o->kappa, Yn, NULL);
         double r = orc_change(n_species, Y, Yn, o->y_floor);
         int accept = r <= o->tol;
@@ -328,6 +413,75 @@ void orc_rhs_f32(int32_t n_species, int32_t n_reactions, const int32_t *ra, cons
     }
 }
 
+/* The chunked row sums of orc_rhs_rows, in float. */
+static float orc_row_sum_f32(const float *t, int32_t n, int32_t split_above)
+{
+    if (split_above <= 0 || n <= split_above) {
+        float s = 0.0f;
+        for (int32_t q = 0; q < n; ++q)
+            s += t[q];
+        return s;
+    }
+    const int32_t chunk = orc_chunk_terms(split_above);
+    float total = 0.0f;
+    for (int32_t first = 0; first < n; first += chunk) {
+        float s = 0.0f;
+        for (int32_t q = first; q < n && q < first + chunk; ++q)
+            s += t[q];
+        total = first == 0 ? s : total + s;
+    }
+    return total;
+}
+
+void orc_rhs_rows_f32(int32_t n_species, int32_t n_reactions, const int32_t *ra,
+                      const int32_t *rb, const int32_t *rc, const float *kf, const float *yf,
+                      int32_t split_above, float *fpf, float *kdf)
+{
+    if (split_above <= 0) {
+        orc_rhs_f32(n_species, n_reactions, ra, rb, rc, kf, yf, fpf, kdf);
+        return;
+    }
+    int32_t *nF = calloc((size_t)n_species, sizeof(int32_t));
+    int32_t *nK = calloc((size_t)n_species, sizeof(int32_t));
+    int32_t *oF = malloc(sizeof(int32_t) * (size_t)(n_species + 1));
+    int32_t *oK = malloc(sizeof(int32_t) * (size_t)(n_species + 1));
+    float *tF = malloc(sizeof(float) * (size_t)(n_reactions + 1));
+    float *tK = malloc(sizeof(float) * (size_t)(2 * n_reactions + 1));
+    for (int32_t j = 0; j < n_reactions; ++j) {
+        nF[rc[j]]++;
+        nK[ra[j]]++;
+        if (rb[j] >= 0)
+            nK[rb[j]]++;
+    }
+    oF[0] = oK[0] = 0;
+    for (int32_t i = 0; i < n_species; ++i) {
+        oF[i + 1] = oF[i] + nF[i];
+        oK[i + 1] = oK[i] + nK[i];
+        nF[i] = nK[i] = 0;
+    }
+    for (int32_t j = 0; j < n_reactions; ++j) {
+        const float kj = kf[j];
+        if (rb[j] < 0) {
+            tF[oF[rc[j]] + nF[rc[j]]++] = kj * yf[ra[j]];
+            tK[oK[ra[j]] + nK[ra[j]]++] = kj;
+        } else {
+            tF[oF[rc[j]] + nF[rc[j]]++] = (kj * yf[ra[j]]) * yf[rb[j]];
+            tK[oK[ra[j]] + nK[ra[j]]++] = kj * yf[rb[j]];
+            tK[oK[rb[j]] + nK[rb[j]]++] = kj * yf[ra[j]];
+        }
+    }
+    for (int32_t i = 0; i < n_species; ++i) {
+        fpf[i] = orc_row_sum_f32(tF + oF[i], nF[i], split_above);
+        kdf[i] = orc_row_sum_f32(tK + oK[i], nK[i], split_above);
+    }
+    free(nF);
+    free(nK);
+    free(oF);
+    free(oK);
+    free(tF);
+    free(tK);
+}
+
 /* The kappa-switched update as orc_update, in float. */
 void orc_update_f32(int32_t n_species, const float *yf, const float *fpf, const float *kdf,
                     float hf, float kappaf, float *ynf)
@@ -401,7 +555,7 @@ int32_t orc_integrate_zone_f32(int32_t n_species, int32_t n_reactions, const int
         }
         const int last = trial >= t_end - tt;
         const double hh = last ? t_end - tt : trial;
-        orc_rhs_f32(n_species, n_reactions, a, b, c, kf, Yf, Fp, kd);
+        orc_rhs_rows_f32(n_species, n_reactions, a, b, c, kf, Yf, o->split_above, Fp, kd);
         orc_update_f32(n_species, Yf, Fp, kd, (float)hh, kappa, Yn);
         const double rr = (double)orc_change_f32(n_species, Yf, Yn, y_floor);
         if (rr <= o->tol) {
@@ -774,7 +928,7 @@ static double orc_boundary_label(int32_t n_species, int32_t n_reactions, const i
                                  const double *Y, double h, const orc_options *o,
                                  const double *pow2, double *Fp, double *kd, double *Yn)
 {
-    orc_rhs(n_species, n_reactions, a, b, c, k, Y, Fp, kd);
+    orc_rhs_rows(n_species, n_reactions, a, b, c, k, Y, o->split_above, Fp, kd);
     int lo = -97, hi = 97;
     while (hi - lo > 1) {
         const int mid = lo + (hi - lo) / 2;
@@ -857,7 +1011,7 @@ int32_t orc_integrate_zone_learned(int32_t n_species, int32_t n_reactions, const
         }
         int clipped = step >= t_end - t;
         double h = clipped ? t_end - t : step;
-        orc_rhs(n_species, n_reactions, a, b, c, k, Y, Fp, kd);
+        orc_rhs_rows(n_species, n_reactions, a, b, c, k, Y, o->split_above, Fp, kd);
         orc_update(n_species, Y, Fp, kd, h, o->kappa, Yn, NULL);
         double r = orc_change(n_species, Y, Yn, o->y_floor);
         if (r <= o->tol) {

@@ -1,11 +1,11 @@
 """GPU integration of a network with hub species (3 species in about 200 reactions each).
 
 Rows of more than 64 terms are summed in chunks of 32 consecutive terms whose partial sums are
-then added in order, so the hub rows round differently from the oracle's one-pass ascending sum
-(all terms are non-negative: the difference is a few ulps).  Bar: the parity bar of the double
-path (relative error <= 1e-9 on every species above 1e-20, accepted steps within 1 %, identical
-status).  The chunking does not depend on the launch, so all launch configurations agree bit for
-bit.
+then added in order.  The oracle sums rows in that order too when asked (options split_above),
+so the GPU must match it bit for bit, in double and in single precision; against the oracle's
+one-pass sums the chunked order moves results by a few ulps per sum, which the stiff steps carry
+to at most 1e-8 relative.  The chunking does not depend on the launch, so all launch
+configurations agree bit for bit.
 """
 import sys
 
@@ -75,29 +75,38 @@ def test_hub_network_is_split_and_packed():
         h.close()
 
 
+def same(g, ref, idx=None):
+    idx = slice(None) if idx is None else idx
+    np.testing.assert_array_equal(g["zone_status"][idx], ref["status"])
+    np.testing.assert_array_equal(g["n_accepted"][idx], ref["n_acc"])
+    np.testing.assert_array_equal(g["n_rejected"][idx], ref["n_rej"])
+    np.testing.assert_array_equal(g["dt"][idx], ref["dt"])
+    np.testing.assert_array_equal(g["Y"][idx], ref["Y"])
+
+
 def test_hub_parity_full_batch_every_zone():
-    """Every zone of the hub batch.  The hub rows are summed in chunks whose sums are then added
-    in order, a different order of the same additions than the oracle's one pass: each sum
-    differs by a few ulps, and over thousands of stiff steps a few species whose value comes
-    out of a near-cancellation carry that further.  Bar: statuses equal, accepted steps within
-    1 %, every species above 1e-20 within 1e-8 relative and all but 1 in 1e5 within 1e-9."""
+    """Every zone of the hub batch, bit for bit against the oracle summing long rows in the same
+    chunks.  Against the one-pass oracle (definition order) each hub sum differs by a few ulps,
+    which a few species that come out of a near-cancellation carry further over thousands of
+    stiff steps: statuses equal, accepted steps within 1 %, every species above 1e-20 within
+    1e-8 relative and all but 1 in 1e5 within 1e-9."""
     wl = workloads.preset(NAME)
     say(f"case hub {NAME} zones={wl.zones.n_zones} all zones")
     g = run(wl)
+    same(g, oracle.integrate_batch(wl.network, wl.zones, opts=oracle.options(split_above=64)))
     ref = oracle.integrate_batch(wl.network, wl.zones)
     np.testing.assert_array_equal(g["zone_status"], ref["status"])
     assert (np.abs(g["n_accepted"] - ref["n_acc"]) <= 0.01 * ref["n_acc"]).all()
     big = ref["Y"] > 1e-20
     rel = np.abs(g["Y"] - ref["Y"])[big] / ref["Y"][big]
     over = float(np.mean(rel > 1e-9))
-    say(f"  max rel {rel.max():.2e}, median {np.median(rel):.1e}, share above 1e-9 {over:.1e}, "
-        f"zones with equal accepted steps {np.mean(g['n_accepted'] == ref['n_acc']):.4f}; "
-        f"launch {g['launch']}")
+    say(f"  bit-exact against the chunked oracle; against one pass: max rel {rel.max():.2e}, "
+        f"median {np.median(rel):.1e}, share above 1e-9 {over:.1e}; launch {g['launch']}")
     assert rel.max() <= 1e-8 and over <= 1e-5
     assert (g["zone_status"] == binding.ZONE_OK).all()
 
 
-def test_hub_launch_invariance_and_f32():
+def test_hub_launch_invariance():
     wl = workloads.preset(NAME, n_zones=48)
     say("case hub launch invariance zones=48")
     outs = [run(wl, launch=dict(variant=1, threads_per_zone=64 * W, zone_order=zo))
@@ -105,21 +114,22 @@ def test_hub_launch_invariance_and_f32():
     for o in outs[1:]:
         for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
             np.testing.assert_array_equal(o[key], outs[0][key])
-    # single precision: the chunked hub sums round differently in float, and a few thousand
-    # stiff steps amplify that; statuses and step counts still agree, most species to 1e-5
+
+
+def test_hub_f32_full_batch_every_zone():
+    """Single precision, every zone of the hub batch, bit for bit against the single-precision
+    oracle summing long rows in the same chunks."""
+    wl = workloads.preset(NAME)
+    say(f"case hub f32 {NAME} zones={wl.zones.n_zones} all zones")
     g32 = run(wl, precision=1)
-    ref32 = oracle.integrate_batch(wl.network, wl.zones, precision=1)
-    np.testing.assert_array_equal(g32["zone_status"], ref32["status"])
-    assert (np.abs(g32["n_accepted"] - ref32["n_acc"]) <= 0.01 * ref32["n_acc"]).all()
-    big = ref32["Y"] > 1e-20
-    rel = np.abs(g32["Y"] - ref32["Y"])[big] / ref32["Y"][big]
-    say(f"  f32 rel median {np.median(rel):.2e} max {rel.max():.2e}")
-    assert np.median(rel) <= 1e-5 and rel.max() <= 2e-2
+    same(g32, oracle.integrate_batch(wl.network, wl.zones, opts=oracle.options(split_above=64),
+                                     precision=1))
 
 
 def test_split_threshold_option():
-    """A lower split threshold (split_above) chunks the ordinary rows too: the results stay within
-    the parity bar of the oracle and do not depend on the launch."""
+    """A lower split threshold (split_above) chunks the ordinary rows too: the results match the
+    oracle summing in the same chunks bit for bit, stay within the parity bar of the one-pass
+    oracle and do not depend on the launch."""
     import torch
 
     wl = workloads.preset("n150_r1604_arrhenius", n_zones=24)
@@ -137,5 +147,8 @@ def test_split_threshold_option():
             net.close()
     for key in ("Y", "dt", "n_accepted", "n_rejected", "zone_status"):
         np.testing.assert_array_equal(outs[1][key], outs[0][key])
+    same(outs[0], oracle.integrate_batch(wl.network, wl.zones,
+                                         opts=oracle.options(split_above=24)))
     ref = oracle.integrate_batch(wl.network, wl.zones)
-    say(f"  max rel {check(outs[0], ref, np.arange(24), 1e-9, 1e-20):.2e}")
+    say(f"  bit-exact against the oracle in chunks of 12; against one pass max rel "
+        f"{check(outs[0], ref, np.arange(24), 1e-9, 1e-20):.2e}")

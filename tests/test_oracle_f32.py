@@ -119,3 +119,14 @@ def test_statuses_in_float():
         args = dict(ok, **change)
         out = oracle.integrate_zone_f32(DECAY, args["k"], args["Y0"], args["t_end"], args["dt0"])
         assert out["status"] == status
+
+
+@pytest.mark.parametrize("split_above,offset", [(0, 0), (8, 36), (12, 36), (39, 24), (40, 0)])
+def test_long_rows_summed_in_chunks_in_float(split_above, offset):
+    """The chunked row sums in float: 2^24 plus 39 ones.  One pass loses every +1 (ties to even);
+    in chunks of c terms the row is 2^24 + (40 - c) exactly."""
+    from tests.test_oracle_pins import long_row_net, long_row_sums
+
+    net = long_row_net()
+    fp, kd = long_row_sums(net, 2.0 ** 24, 1.0, split_above, rhs=oracle.rhs_f32, dtype=np.float32)
+    assert fp == kd == np.float32(2.0 ** 24 + offset)

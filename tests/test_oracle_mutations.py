@@ -39,6 +39,15 @@ MUTATIONS = {
     "f32_partner_index": ("kdf[ra[j]] += kj * yf[rb[j]];", "kdf[ra[j]] += kj * yf[ra[j]];"),
     "f32_change_against_new_state": ("fmaxf(yf[i], floorf_)", "fmaxf(ynf[i], floorf_)"),
     "f32_state_kept_double": ("        Yf[i] = (float)Y[i];", "        Yf[i] = (float)(Y[i] * 1.0000001);"),
+    # chunked sums of long rows
+    "chunk_not_multiple_of_4": ("    const int32_t chunk = split_above / 2 / 4 * 4;",
+                                "    const int32_t chunk = split_above / 2;"),
+    "row_of_split_above_terms_split": ("    if (split_above <= 0 || n <= split_above) {\n        double s",
+                                       "    if (split_above <= 0 || n < split_above) {\n        double s"),
+    "chunk_sum_not_restarted": ("        double s = 0.0;\n        for (int32_t q = first;",
+                                "        double s = total;\n        for (int32_t q = first;"),
+    "f32_chunk_sum_not_restarted": ("        float s = 0.0f;\n        for (int32_t q = first;",
+                                    "        float s = total;\n        for (int32_t q = first;"),
 }
 
 # mistakes in the learned-controller reference (the part of oracle.c after LEARNED_MARK)

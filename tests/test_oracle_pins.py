@@ -422,3 +422,65 @@ def test_rate_exponential_within_one_ulp_of_the_library():
     assert abs(oracle.exp_cw(1.0) - math.e) <= np.spacing(math.e)
     assert oracle.exp_cw(800.0) == math.inf and oracle.exp_cw(-800.0) == 0.0
     assert math.isnan(oracle.exp_cw(math.nan))
+
+
+# --- chunked summation of long rows (hub species) -----------------------------------------------
+
+def long_row_net():
+    """Species 0 (P) and 40 others: reactions 0..39 are X_j -> P, reactions 40..79 are P -> X_j,
+    so that with every Y = 1 the F+ row and the k row of P both hold the 40 rates in order."""
+    reactions = [(j, -1, 0) for j in range(1, 41)] + [(0, -1, j) for j in range(1, 41)]
+    return net_from(reactions, [1] * 41)
+
+
+def long_row_sums(net, first, rest, split_above, rhs=oracle.rhs, dtype=np.float64):
+    """F+ and k of P with rates (first, rest x 39) on both rows and every Y = 1."""
+    k = np.array(([first] + [rest] * 39) * 2, dtype=np.float64)
+    Fp, kd = rhs(net, k, np.ones(net.n_species), split_above=split_above)
+    return dtype(Fp[0]), dtype(kd[0])
+
+
+@pytest.mark.parametrize("split_above,offset", [(0, 0), (8, 36), (12, 36), (39, 24), (40, 0)])
+def test_long_rows_summed_in_chunks(split_above, offset):
+    """Row of 40 terms 2^53, 1, ..., 1.  One pass: every +1 is a tie that rounds back to 2^53.
+    In chunks of c terms the first chunk is 2^53 and every other chunk sums exactly, so the row
+    is 2^53 + (40 - c).  c = split_above / 2 rounded down to a multiple of 4: 4 for 8 and for 12,
+    16 for 39; a row of exactly split_above terms (40) is not split."""
+    net = long_row_net()
+    fp, kd = long_row_sums(net, 2.0 ** 53, 1.0, split_above)
+    assert fp == kd == 2.0 ** 53 + offset
+
+
+def test_chunk_sums_are_added_in_chunk_order():
+    """Rates 2^53, 0, 0, 0, then 36 x 1/4, in chunks of 4: the chunk sums are 2^53 then nine
+    times 1.0.  Added in chunk order every 1.0 is a tie that rounds back to 2^53; added the other
+    way they would make 2^53 + 8."""
+    net = long_row_net()
+    k = np.array(([2.0 ** 53, 0.0, 0.0, 0.0] + [0.25] * 36) * 2)
+    Fp, kd = oracle.rhs(net, k, np.ones(net.n_species), split_above=8)
+    assert Fp[0] == kd[0] == 2.0 ** 53
+    assert Fp[1:].tolist() == k[40:].tolist()
+
+
+def test_chunked_rows_change_only_the_long_rows():
+    """On the hub network: rows of at most 64 terms are bit-identical to the one-pass sums; the
+    three hub depletion rows differ by at most the rounding bound of a sum of non-negative terms
+    (n eps times the sum); a threshold above every row length is the one-pass sum."""
+    wl = workloads.preset("n150_r1604_hub_arrhenius", n_zones=4)
+    net = wl.network
+    P, D = dense_incidence(net)
+    rows_k = (D != 0).sum(axis=1)
+    rows_f = (P != 0).sum(axis=1)
+    for z in range(4):
+        k = oracle.rates_arrhenius(net.A, net.E, wl.zones.T[z])
+        Y = wl.zones.Y0[z]
+        F0, k0 = oracle.rhs(net, k, Y)
+        F1, k1 = oracle.rhs(net, k, Y, split_above=64)
+        F2, k2 = oracle.rhs(net, k, Y, split_above=10 ** 6)
+        assert np.array_equal(F0, F2) and np.array_equal(k0, k2)
+        assert np.array_equal(F0[rows_f <= 64], F1[rows_f <= 64])
+        assert np.array_equal(k0[rows_k <= 64], k1[rows_k <= 64])
+        long = rows_k > 64
+        assert long.sum() == 3
+        bound = rows_k[long] * np.finfo(np.float64).eps * k0[long]
+        assert (np.abs(k1[long] - k0[long]) <= bound).all()
