@@ -242,6 +242,10 @@ typedef struct {
     int64_t gather_cycles_packed;  /* modelled LDS cycles of one zone-step's gathers (the gfx950
                                       bank rules) in packing order ... */
     int64_t gather_cycles_placed;  /* ... and after the bank-aware placement */
+    int32_t one_factor_slots;      /* leading slots in which every lane's terms have 1.0 as second
+                                      factor (whole blocks of 4) */
+    int32_t one_factor_slots_run;  /* of those, the slots the double-precision plain kernel runs
+                                      without the second gather on every wave */
 } asy_layout_info;
 
 /*

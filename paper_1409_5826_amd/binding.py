@@ -115,6 +115,8 @@ class asy_layout_info(C.Structure):
         ("one_factor_waves", C.c_uint32),
         ("gather_cycles_packed", C.c_int64),
         ("gather_cycles_placed", C.c_int64),
+        ("one_factor_slots", C.c_int32),
+        ("one_factor_slots_run", C.c_int32),
     ]
 
     def as_dict(self):

@@ -45,6 +45,7 @@ struct StratLayout {
     int n_split = 0;      // rows summed in chunks
     int64_t gather_cycles_before = 0, gather_cycles_after = 0;  // modelled, per zone-step
     uint32_t one_waves = 0;  // waves whose terms all have 1.0 as second factor
+    int f1 = 0;           // leading slots whose terms all have 1.0 as second factor
     bool ok32 = false;    // the single-precision tables exist
     StratNetwork sn32{};  // the same layout with descriptors for float cells
     void *dev = nullptr;
@@ -133,9 +134,11 @@ using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *,
 // mode: 0 plain controller, 1 plain with trace, 2 learned, 3 learned with trace,
 //       4 plain controller in single precision
 // CR: slots whose rates the instance keeps in registers (the rest in LDS)
+// F1: leading slots the instance runs as one-factor terms on every wave (0: none)
 struct StratInstance {
     int W, SPL, C, CR, mode;
     StratKernel fn;
+    int F1 = 0;
 };
 
 #define ASY_STRAT(W_, SPL_, C_)                                                                 \
@@ -146,6 +149,12 @@ struct StratInstance {
 #define ASY_STRAT_F32(W_, SPL_, C_)                                                             \
     {W_, SPL_, C_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_, float>(), false, \
                                                false, float>}
+#define ASY_STRAT_F1(W_, SPL_, C_, CR_, F1_)                                                    \
+    {W_, SPL_, C_, CR_, 0, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<CR_>(), false,    \
+                                                false, double, CR_, F1_>, F1_}
+#define ASY_STRAT_F32_F1(W_, SPL_, C_, F1_)                                                     \
+    {W_, SPL_, C_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_, float>(), false, \
+                                               false, float, C_, F1_>, F1_}
 #define ASY_STRAT_LEARN(W_, SPL_, C_)                                                           \
     {W_, SPL_, C_, C_, 1, integrate_strat_kernel<W_, SPL_, C_, 2, false, true>},                \
     {W_, SPL_, C_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                \
@@ -166,18 +175,26 @@ const StratInstance kStratInstances[] = {
     ASY_STRAT_F32(2, 3, 104), ASY_STRAT_F32(2, 3, 112),
     ASY_STRAT_F32(4, 1, 16), ASY_STRAT_F32(4, 1, 32), ASY_STRAT_F32(4, 1, 40), ASY_STRAT_F32(4, 1, 48),
     ASY_STRAT_F32(4, 2, 48), ASY_STRAT_F32(4, 2, 56), ASY_STRAT_F32(4, 2, 64), ASY_STRAT_F32(4, 2, 80),
+    ASY_STRAT_F1(2, 2, 40, 40, 8), ASY_STRAT_F32_F1(2, 2, 40, 8),
+    ASY_STRAT_F1(4, 2, 56, 40, 16), ASY_STRAT_F32_F1(4, 2, 56, 16),
 };
 #undef ASY_STRAT
 #undef ASY_STRAT_CR
+#undef ASY_STRAT_F1
 #undef ASY_STRAT_F32
+#undef ASY_STRAT_F32_F1
 #undef ASY_STRAT_LEARN
 
-const StratInstance *find_strat_instance(int W, int SPL, int C_needed, int mode = 0)
+// The instance for a layout: the smallest C that holds C_needed slots, and of those the one
+// with the most leading one-factor slots the layout allows (f1_max, from build_strat).
+const StratInstance *find_strat_instance(int W, int SPL, int C_needed, int mode = 0,
+                                         int f1_max = 0)
 {
     const StratInstance *best = nullptr;
     for (const auto &in : kStratInstances)
         if (in.W == W && in.SPL == SPL && in.mode == mode && in.C >= C_needed &&
-            (!best || in.C < best->C))
+            in.F1 <= f1_max &&
+            (!best || in.C < best->C || (in.C == best->C && in.F1 > best->F1)))
             best = &in;
     return best;
 }
@@ -386,7 +403,11 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         }
         lp.lane_rows = lane_rows;
         lp.lane_start = lane_start;
+        // a lane's one-factor rows stay ahead of its other rows, which keeps the other rows in
+        // the lane's last slots (the leading one-factor slots below)
         lp.row_class.assign(rows.size(), 0);
+        for (size_t r = 0; r < rows.size(); ++r)
+            lp.row_class[r] = one_factor[r] ? 0 : 1;
         const LayoutResult lr = optimise_gather_layout(lp, kLayoutIters, 0x5eed0001ull + W);
         lane_rows = lr.lane_rows;
         lane_start = lr.lane_start;
@@ -470,6 +491,16 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
             one_waves |= 1u << w;
     }
     L.one_waves = one_waves;
+    // leading slots in which no lane holds a term with a second factor other than 1.0 (whole
+    // blocks); instances with that many one-factor slots or fewer can run the layout
+    int f1 = C;
+    for (int l = 0; l < lanes; ++l)
+        for (int s = 0; s < f1; ++s)
+            if (((desc[0][desc_index(s, l, lanes)] >> 16) & 0x7fffu) != (uint32_t)N * 8u) {
+                f1 = s / 4 * 4;
+                break;
+            }
+    L.f1 = f1;
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
@@ -516,7 +547,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         sn.xch = (n_cells * B + 255) / 256 * 256;
         sn.tab = sn.xch + kStratXchBytes;
         // rates of the slots the plain instance does not keep in registers
-        const StratInstance *pi = find_strat_instance(W, L.SPL, L.C, p == 0 ? 0 : 4);
+        const StratInstance *pi = find_strat_instance(W, L.SPL, L.C, p == 0 ? 0 : 4, L.f1);
         const int spill_slots = pi ? pi->C - pi->CR : 0;
         sn.rlds = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
         sn.feat = sn.rlds + spill_slots * lanes * B;
@@ -673,7 +704,7 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
                 return e;
             order = cb.order;
         }
-        const StratInstance *inst = find_strat_instance(W, L.SPL, L.C, mode);
+        const StratInstance *inst = find_strat_instance(W, L.SPL, L.C, mode, L.f1);
         if (!inst)
             return hipErrorInvalidDeviceFunction;
         if (mode >= 1 && mode <= 3)
@@ -1259,6 +1290,9 @@ asy_status asy_network_layout_info(const asy_network *net, int32_t threads_per_z
     info->one_factor_waves = L.one_waves;
     info->gather_cycles_packed = L.gather_cycles_before;
     info->gather_cycles_placed = L.gather_cycles_after;
+    info->one_factor_slots = L.f1;
+    const StratInstance *in = find_strat_instance(L.W, L.SPL, L.C, 0, L.f1);
+    info->one_factor_slots_run = in ? in->F1 : 0;
     return ASY_OK;
 }
 

@@ -256,8 +256,11 @@ constexpr int strat_gather_ahead()
 // CR: the slots whose rates live in registers (the rest are read from LDS every step, one
 // conflict-free read per slot: lanes read consecutive cells), which lets a network that needs
 // many slots keep the register budget -- and occupancy -- of CR slots.
+// F1: leading slots that hold only terms with the 1.0 cell as second factor on every lane (the
+// host packs a lane's rows with such terms first and verifies the layout), so the waves that do
+// run two-factor terms skip the second gather and the product by 1.0 there too (exact).
 template <int W, int SPL, int C, int GA = 2, bool LEARNED = false, bool TRACE = false,
-          typename T = double, int CR = C>
+          typename T = double, int CR = C, int F1 = 0>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
                                amdgpu_waves_per_eu(strat_waves_per_eu<CR, T>())))
 integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates,
@@ -267,6 +270,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     static_assert(!FEATURES || sizeof(T) == 8, "learned controller and trace in double only");
     static_assert(C % 4 == 0, "slots come in blocks of 4");
     static_assert(CR % 4 == 0 && CR <= C, "register-held rates cover whole blocks");
+    static_assert(F1 % 4 == 0 && F1 <= C, "one-factor slots cover whole blocks");
     static_assert(W <= 4, "the exchange area holds 4 waves");
     constexpr int LANES = 64 * W;
     extern __shared__ double lds[];
@@ -469,7 +473,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                 auto rate_of = [&](int s) -> T { return s < CR ? kr[s < CR ? s : 0] : kl[s]; };
                 auto gather = [&](int s) {
                     gx[s] = lds_ld<T>(dq[s] & 0xffffu);
-                    if constexpr (!ONE)
+                    if (!ONE && s >= F1)  // s is a constant of the unrolled loops
                         gy[s] = lds_ld<T>((dq[s] >> 16) & 0x7fffu);
                     if (s >= CR)
                         kl[s] = lds_ld<T>(rl_lane + (uint32_t)((s - CR) * LANES * (int)sizeof(T)));
@@ -488,7 +492,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         gather(s);
 #pragma unroll
                     for (int s = 4 * b; s < 4 * b + 4; ++s) {
-                        if constexpr (ONE)  // second factor 1.0: the product by 1.0 is exact
+                        if (ONE || s < F1)  // second factor 1.0: the product by 1.0 is exact
                             acc = acc + rate_of(s) * gx[s];
                         else
                             acc = acc + (rate_of(s) * gx[s]) * gy[s];
