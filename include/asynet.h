@@ -246,12 +246,17 @@ typedef struct {
                                       factor (whole blocks of 4) */
     int32_t one_factor_slots_run;  /* of those, the slots the double-precision plain kernel runs
                                       without the second gather on every wave */
+    int32_t two_factor_wave_slots; /* slots the waves with two-factor terms run (= slots unless
+                                      the layout is balanced: those waves stop earlier and the
+                                      one-factor waves carry more slots) */
 } asy_layout_info;
 
 /*
- * The variant-1 layout built at creation for threads_per_zone (64, 128 or
- * 256; ASY_EINVAL otherwise).  Host only, no device call.  info: host, out;
- * available = 0 (and the rest zero) when no compiled instance holds it.
+ * The variant-1 layout the plain double-precision kernel runs for
+ * threads_per_zone (64, 128 or 256; ASY_EINVAL otherwise): the balanced layout
+ * where one was built, else the default one.  Host only, no device call.
+ * info: host, out; available = 0 (and the rest zero) when no compiled instance
+ * holds it.
  */
 asy_status asy_network_layout_info(const asy_network *net, int32_t threads_per_zone,
                                    asy_layout_info *info);

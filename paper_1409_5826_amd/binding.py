@@ -117,6 +117,7 @@ class asy_layout_info(C.Structure):
         ("gather_cycles_placed", C.c_int64),
         ("one_factor_slots", C.c_int32),
         ("one_factor_slots_run", C.c_int32),
+        ("two_factor_wave_slots", C.c_int32),
     ]
 
     def as_dict(self):

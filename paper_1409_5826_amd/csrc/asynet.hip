@@ -46,6 +46,7 @@ struct StratLayout {
     int64_t gather_cycles_before = 0, gather_cycles_after = 0;  // modelled, per zone-step
     uint32_t one_waves = 0;  // waves whose terms all have 1.0 as second factor
     int f1 = 0;           // leading slots whose terms all have 1.0 as second factor
+    int C2 = 0;           // balanced layout: slots of the two-factor waves (0: all C)
     bool ok32 = false;    // the single-precision tables exist
     StratNetwork sn32{};  // the same layout with descriptors for float cells
     void *dev = nullptr;
@@ -92,6 +93,7 @@ struct asy_network {
     int32_t *queue = nullptr;
     DevNetwork dn{};
     StratLayout strat[3];       // variant 1 with W = 1, 2, 4
+    StratLayout strat_bal[3];   // balanced variant-1 layouts of the plain kernels (if built)
     double *rate_buf = nullptr; // Arrhenius rates of one call, [zones][reactions]
     size_t rate_buf_zones = 0;
     float *key_buf = nullptr;   // scheduling keys of one call, [zones]
@@ -135,10 +137,12 @@ using StratKernel = void (*)(StratNetwork, DevOptions, ZoneArgs, const double *,
 //       4 plain controller in single precision
 // CR: slots whose rates the instance keeps in registers (the rest in LDS)
 // F1: leading slots the instance runs as one-factor terms on every wave (0: none)
+// C2: slots the waves with two-factor terms run (0: all C, like the other waves)
 struct StratInstance {
     int W, SPL, C, CR, mode;
     StratKernel fn;
     int F1 = 0;
+    int C2 = 0;
 };
 
 #define ASY_STRAT(W_, SPL_, C_)                                                                 \
@@ -155,6 +159,12 @@ struct StratInstance {
 #define ASY_STRAT_F32_F1(W_, SPL_, C_, F1_)                                                     \
     {W_, SPL_, C_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_, float>(), false, \
                                                false, float, C_, F1_>, F1_}
+#define ASY_STRAT_SPLIT(W_, SPL_, C_, CR_, C2_)                                                 \
+    {W_, SPL_, C_, CR_, 0, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<CR_>(), false,    \
+                                                false, double, CR_, 0, C2_>, 0, C2_}
+#define ASY_STRAT_F32_SPLIT(W_, SPL_, C_, CR_, C2_)                                             \
+    {W_, SPL_, C_, CR_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<CR_, float>(),   \
+                                                false, false, float, CR_, 0, C2_>, 0, C2_}
 #define ASY_STRAT_LEARN(W_, SPL_, C_)                                                           \
     {W_, SPL_, C_, C_, 1, integrate_strat_kernel<W_, SPL_, C_, 2, false, true>},                \
     {W_, SPL_, C_, C_, 2, integrate_strat_kernel<W_, SPL_, C_, 2, true, false>},                \
@@ -177,23 +187,27 @@ const StratInstance kStratInstances[] = {
     ASY_STRAT_F32(4, 2, 48), ASY_STRAT_F32(4, 2, 56), ASY_STRAT_F32(4, 2, 64), ASY_STRAT_F32(4, 2, 80),
     ASY_STRAT_F1(2, 2, 40, 40, 8), ASY_STRAT_F32_F1(2, 2, 40, 8),
     ASY_STRAT_F1(4, 2, 56, 40, 16), ASY_STRAT_F32_F1(4, 2, 56, 16),
+    ASY_STRAT_SPLIT(2, 2, 44, 40, 32), ASY_STRAT_F32_SPLIT(2, 2, 44, 40, 32),
 };
 #undef ASY_STRAT
 #undef ASY_STRAT_CR
 #undef ASY_STRAT_F1
 #undef ASY_STRAT_F32
 #undef ASY_STRAT_F32_F1
+#undef ASY_STRAT_SPLIT
+#undef ASY_STRAT_F32_SPLIT
 #undef ASY_STRAT_LEARN
 
 // The instance for a layout: the smallest C that holds C_needed slots, and of those the one
-// with the most leading one-factor slots the layout allows (f1_max, from build_strat).
+// with the most leading one-factor slots the layout allows (f1_max, from build_strat); c2 > 0
+// asks for an instance whose two-factor waves stop at slot c2 (a balanced layout).
 const StratInstance *find_strat_instance(int W, int SPL, int C_needed, int mode = 0,
-                                         int f1_max = 0)
+                                         int f1_max = 0, int c2 = 0)
 {
     const StratInstance *best = nullptr;
     for (const auto &in : kStratInstances)
         if (in.W == W && in.SPL == SPL && in.mode == mode && in.C >= C_needed &&
-            in.F1 <= f1_max &&
+            in.F1 <= f1_max && in.C2 == c2 &&
             (!best || in.C < best->C || (in.C == best->C && in.F1 > best->F1)))
             best = &in;
     return best;
@@ -259,11 +273,15 @@ constexpr int64_t kLayoutIters = 100000;  // annealing moves per layout (~0.4 s 
 // Row sums take the cells after Y in lane order (lane 0's rows first, each
 // lane's in its slot order); split rows' totals follow.  Leaves L.ok false
 // when no compiled instance can hold the layout.
+// bal: build the balanced layout of that instance instead (into strat_bal): the
+// two-factor rows packed into the first C2 slots of as few lanes as a cap allows,
+// the one-factor rows into the rest (C2 slots on the lanes of waves with two-factor
+// rows, C on the others), so the two kinds of wave get about equal work.
 void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &rows_in,
-                 int split_above)
+                 int split_above, const StratInstance *bal = nullptr)
 {
     const int chunk = std::max(4, split_above / 2 / 4 * 4);  // terms per chunk of a split row
-    StratLayout &L = net->strat[w_index(W)];
+    StratLayout &L = bal ? net->strat_bal[w_index(W)] : net->strat[w_index(W)];
     L = StratLayout{};
     const int N = net->n_species;
     const int lanes = 64 * W;
@@ -317,11 +335,12 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L.lanes = lanes;
     L.C_needed = C_needed;
     L.SPL = (N + lanes - 1) / lanes;
-    const StratInstance *inst = find_strat_instance(W, L.SPL, C_needed);
-    if (!inst || C_needed > 256)
+    const StratInstance *inst = bal ? bal : find_strat_instance(W, L.SPL, C_needed);
+    if (!inst || C_needed > 256 || inst->SPL != L.SPL || inst->W != W)
         return;  // end_mask holds at most 64 blocks of 4 slots
     const int C = inst->C;
     L.C = C;
+    L.C2 = bal ? bal->C2 : 0;
     // Rows whose second factors are all the 1.0 cell (depletion rows, creation rows of
     // one-body reactions only) need no second gather and no multiply by 1.0 (exact).  A wave
     // whose lanes hold only such rows runs a slot phase without either, so pack the other
@@ -341,7 +360,59 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         std::vector<std::vector<int>> best_rows;
         std::vector<int> best_load;
         const int cap0 = other.empty() ? 4 : padded(other.front());
-        for (int cap = cap0; cap <= C && best_free < W; cap += 4) {
+        if (bal) {
+            // the smallest cap whose first-fit packing leaves a wave free of two-factor rows
+            // and lets the one-factor rows fit (each onto the lane with the most room left)
+            const int C2 = bal->C2;
+            bool done = false;
+            for (int cap = cap0; cap <= C2 && !done; cap += 4) {
+                std::vector<int> tload(lanes, 0);
+                std::vector<std::vector<int>> lr(lanes), lone(lanes);
+                bool ok = true;
+                int used = 0;
+                for (int r : other) {
+                    int l = 0;
+                    while (l < lanes && tload[l] + padded(r) > cap)
+                        ++l;
+                    if (l == lanes) {
+                        ok = false;
+                        break;
+                    }
+                    tload[l] += padded(r);
+                    lr[l].push_back(r);
+                    used = std::max(used, l + 1);
+                }
+                const int two_waves = (used + 63) / 64;
+                if (!ok || two_waves >= W)
+                    continue;
+                std::vector<int> room(lanes);
+                for (int l = 0; l < lanes; ++l)
+                    room[l] = l < 64 * two_waves ? C2 : C;
+                for (int r : ones) {
+                    int l = 0;
+                    for (int m = 1; m < lanes; ++m)
+                        if (room[m] - tload[m] > room[l] - tload[l])
+                            l = m;
+                    if (tload[l] + padded(r) > room[l]) {
+                        ok = false;
+                        break;
+                    }
+                    tload[l] += padded(r);
+                    lone[l].push_back(r);
+                }
+                if (!ok)
+                    continue;
+                for (int l = 0; l < lanes; ++l) {
+                    lane_rows[l] = lone[l];
+                    lane_rows[l].insert(lane_rows[l].end(), lr[l].begin(), lr[l].end());
+                    lane_start[l] = room[l] - tload[l];
+                }
+                done = true;
+            }
+            if (!done)
+                return;
+        }
+        for (int cap = cap0; cap <= C && best_free < W && !bal; cap += 4) {
             std::vector<int> tload(lanes, 0);
             std::vector<std::vector<int>> lr(lanes), lone(lanes);
             bool ok = true;
@@ -491,6 +562,14 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
             one_waves |= 1u << w;
     }
     L.one_waves = one_waves;
+    if (bal) {  // the waves with two-factor terms hold nothing past slot C2
+        const uint32_t pad = (uint32_t)N * 8u | ((uint32_t)N * 8u << 16);
+        for (int l = 0; l < lanes; ++l)
+            if (!((one_waves >> (l / 64)) & 1u))
+                for (int s = L.C2; s < C; ++s)
+                    if (desc[0][desc_index(s, l, lanes)] != pad || rx[(size_t)s * lanes + l] != -1)
+                        return;
+    }
     // leading slots in which no lane holds a term with a second factor other than 1.0 (whole
     // blocks); instances with that many one-factor slots or fewer can run the layout
     int f1 = C;
@@ -547,7 +626,7 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         sn.xch = (n_cells * B + 255) / 256 * 256;
         sn.tab = sn.xch + kStratXchBytes;
         // rates of the slots the plain instance does not keep in registers
-        const StratInstance *pi = find_strat_instance(W, L.SPL, L.C, p == 0 ? 0 : 4, L.f1);
+        const StratInstance *pi = find_strat_instance(W, L.SPL, L.C, p == 0 ? 0 : 4, L.f1, L.C2);
         const int spill_slots = pi ? pi->C - pi->CR : 0;
         sn.rlds = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
         sn.feat = sn.rlds + spill_slots * lanes * B;
@@ -577,9 +656,21 @@ size_t lds_bytes_variant0(const asy_network *net)
 
 // LDS of one workgroup of variant 1: mode 4 (single precision) has float cells;
 // modes 1-3 (traces, learned controller) add the network's input and hidden layers.
+// The layout a kernel family runs with W waves per zone: the balanced layout for the plain
+// controller (double or single precision) where it was built and an instance exists, else the
+// default layout, which every family can run.
+const StratLayout &layout_for(const asy_network *net, int W, int mode)
+{
+    const StratLayout &B = net->strat_bal[w_index(W)];
+    if ((mode == 0 || mode == 4) && B.ok && (mode == 0 || B.ok32) &&
+        find_strat_instance(W, B.SPL, B.C, mode, B.f1, B.C2))
+        return B;
+    return net->strat[w_index(W)];
+}
+
 size_t lds_bytes_variant1(const asy_network *net, int W, int mode)
 {
-    const StratLayout &L = net->strat[w_index(W)];
+    const StratLayout &L = layout_for(net, W, mode);
     const bool features = mode >= 1 && mode <= 3;
     return strat_lds_bytes(mode == 4 ? L.sn32.feat : L.sn.feat, features);
 }
@@ -613,7 +704,8 @@ asy_status validate_launch(const asy_network *net, const asy_launch *c)
         if (!net->strat[w_index(W)].ok)
             return fail(ASY_ENOTSUP, "variant 1 has no kernel instance for this network with " +
                                          std::to_string(c->threads_per_zone) + " threads per zone");
-        if (lds_bytes_variant1(net, W, 1) > net->lds_per_group_max)
+        if (std::max(lds_bytes_variant1(net, W, 0), lds_bytes_variant1(net, W, 1)) >
+            net->lds_per_group_max)
             return fail(ASY_ENOTSUP, "variant 1: zones do not fit the LDS of one workgroup");
         return ASY_OK;
     }
@@ -675,7 +767,7 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
         return e;
     if (c.variant == 1) {
         const int W = c.threads_per_zone / 64;
-        const StratLayout &L = net->strat[w_index(W)];
+        const StratLayout &L = layout_for(net, W, mode);
         const double *rates = za.k_zone;
         if (net->rate_form == ASY_RATES_ARRHENIUS) {
             const size_t total = (size_t)za.n_zones * net->n_reactions;
@@ -704,7 +796,7 @@ hipError_t launch_all(asy_network *net, const asy_launch &c, const DevOptions &o
                 return e;
             order = cb.order;
         }
-        const StratInstance *inst = find_strat_instance(W, L.SPL, L.C, mode, L.f1);
+        const StratInstance *inst = find_strat_instance(W, L.SPL, L.C, mode, L.f1, L.C2);
         if (!inst)
             return hipErrorInvalidDeviceFunction;
         if (mode >= 1 && mode <= 3)
@@ -1201,8 +1293,20 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
     {
         const auto rows = network_rows(N, R, d->reactant0, d->reactant1, d->product);
         const int split_above = d->split_above > 0 ? d->split_above : kSplitAboveDefault;
-        for (int W : {1, 2, 4})
+        for (int W : {1, 2, 4}) {
             build_strat(net, W, rows, split_above);
+            // a balanced layout for the plain kernels where the default one frees a wave of
+            // second gathers and an instance for it exists (the first that packs)
+            const StratLayout &L = net->strat[w_index(W)];
+            if (!L.ok || !L.one_waves)
+                continue;
+            for (const auto &in : kStratInstances)
+                if (in.mode == 0 && in.C2 > 0 && in.W == W && in.SPL == L.SPL) {
+                    build_strat(net, W, rows, split_above, &in);
+                    if (net->strat_bal[w_index(W)].ok)
+                        break;
+                }
+        }
     }
     // default launch: variant 1 with the least slot work per zone step (slots
     // per lane x waves), slots beyond 64 per lane weighted 1.25 for the
@@ -1250,6 +1354,9 @@ void asy_network_destroy(asy_network *net)
     for (auto &L : net->strat)
         if (L.dev)
             (void)hipFree(L.dev);
+    for (auto &L : net->strat_bal)
+        if (L.dev)
+            (void)hipFree(L.dev);
     if (net->mlp_block)
         (void)hipFree(net->mlp_block);
     if (net->sched_block)
@@ -1278,7 +1385,7 @@ asy_status asy_network_layout_info(const asy_network *net, int32_t threads_per_z
         return fail(ASY_EINVAL, "net and info must be non-NULL");
     if (threads_per_zone != 64 && threads_per_zone != 128 && threads_per_zone != 256)
         return fail(ASY_EINVAL, "threads_per_zone must be 64, 128 or 256");
-    const StratLayout &L = net->strat[w_index(threads_per_zone / 64)];
+    const StratLayout &L = layout_for(net, threads_per_zone / 64, 0);
     *info = asy_layout_info{};
     if (!L.ok)
         return ASY_OK;
@@ -1291,8 +1398,9 @@ asy_status asy_network_layout_info(const asy_network *net, int32_t threads_per_z
     info->gather_cycles_packed = L.gather_cycles_before;
     info->gather_cycles_placed = L.gather_cycles_after;
     info->one_factor_slots = L.f1;
-    const StratInstance *in = find_strat_instance(L.W, L.SPL, L.C, 0, L.f1);
+    const StratInstance *in = find_strat_instance(L.W, L.SPL, L.C, 0, L.f1, L.C2);
     info->one_factor_slots_run = in ? in->F1 : 0;
+    info->two_factor_wave_slots = L.C2 > 0 ? L.C2 : L.C;
     return ASY_OK;
 }
 
@@ -1321,8 +1429,8 @@ asy_status resolve_mode(const asy_network *net, const asy_options &o, bool trace
             return fail(ASY_ENOTSUP, "single precision supports the plain controller without trace");
         if (net->launch.variant != 1)
             return fail(ASY_ENOTSUP, "single precision needs launch variant 1");
-        const StratLayout &L = net->strat[w_index(net->launch.threads_per_zone / 64)];
-        if (!L.ok32 || !find_strat_instance(L.W, L.SPL, L.C, 4))
+        const StratLayout &L = layout_for(net, net->launch.threads_per_zone / 64, 4);
+        if (!L.ok32 || !find_strat_instance(L.W, L.SPL, L.C, 4, L.f1, L.C2))
             return fail(ASY_ENOTSUP, "no single-precision kernel instance for this network and "
                                      "launch configuration");
         mode = 4;
@@ -1580,8 +1688,8 @@ asy_status asy_autotune(asy_network *net, const asy_options *opts, int32_t sampl
     const int mode = o.precision == ASY_PREC_F32 ? 4 : 0;
     std::vector<asy_launch> cands;
     for (int W : {1, 2, 4}) {
-        const StratLayout &L = net->strat[w_index(W)];
-        if (!L.ok || (mode == 4 && (!L.ok32 || !find_strat_instance(W, L.SPL, L.C, 4))))
+        const StratLayout &L = layout_for(net, W, mode);
+        if (!L.ok || (mode == 4 && (!L.ok32 || !find_strat_instance(W, L.SPL, L.C, 4, L.f1, L.C2))))
             continue;
         for (int zo : {1, 0}) {
             asy_launch c{1, 64 * W, 1, 0, 0, zo};

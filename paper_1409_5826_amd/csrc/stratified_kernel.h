@@ -259,8 +259,11 @@ constexpr int strat_gather_ahead()
 // F1: leading slots that hold only terms with the 1.0 cell as second factor on every lane (the
 // host packs a lane's rows with such terms first and verifies the layout), so the waves that do
 // run two-factor terms skip the second gather and the product by 1.0 there too (exact).
+// C2: slots of the waves that hold two-factor terms; their lanes' rows all end by slot C2 (the
+// host packs them so), and they stop there, while the one-factor waves run all C slots -- the
+// two kinds of wave get about equal work per step.
 template <int W, int SPL, int C, int GA = 2, bool LEARNED = false, bool TRACE = false,
-          typename T = double, int CR = C, int F1 = 0>
+          typename T = double, int CR = C, int F1 = 0, int C2 = C>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
                                amdgpu_waves_per_eu(strat_waves_per_eu<CR, T>())))
 integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double *rates,
@@ -271,6 +274,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     static_assert(C % 4 == 0, "slots come in blocks of 4");
     static_assert(CR % 4 == 0 && CR <= C, "register-held rates cover whole blocks");
     static_assert(F1 % 4 == 0 && F1 <= C, "one-factor slots cover whole blocks");
+    static_assert(C2 % 4 == 0 && F1 <= C2 && C2 <= C, "two-factor waves run whole blocks");
     static_assert(W <= 4, "the exchange area holds 4 waves");
     constexpr int LANES = 64 * W;
     extern __shared__ double lds[];
@@ -468,6 +472,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             // the 1.0 cell, no second gathers and no products by 1.0 (exact)
             auto slot_phase = [&](auto one_tag) {
                 constexpr bool ONE = decltype(one_tag)::value;
+                constexpr int NBP = ONE ? NB : C2 / 4;  // blocks this kind of wave runs
                 T gx[C], gy[C], kl[C];
                 // slot s's rate: a register, or (s >= CR) an LDS read issued with its gathers
                 auto rate_of = [&](int s) -> T { return s < CR ? kr[s < CR ? s : 0] : kl[s]; };
@@ -479,16 +484,17 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         kl[s] = lds_ld<T>(rl_lane + (uint32_t)((s - CR) * LANES * (int)sizeof(T)));
                 };
 #pragma unroll
-                for (int s = 0; s < 4 * kGatherAhead && s < C; ++s)
+                for (int s = 0; s < 4 * kGatherAhead && s < 4 * NBP; ++s)
                     gather(s);
                 T acc = (T)0.0;
                 uint32_t wp = wbase;
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    if (b + kDescAhead < NB)
+                for (int b = 0; b < NBP; ++b) {
+                    if (b + kDescAhead < NBP)
                         load_block(b + kDescAhead);
 #pragma unroll
-                    for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < C; ++s)
+                    for (int s = 4 * (b + kGatherAhead); s < 4 * (b + kGatherAhead + 1) && s < 4 * NBP;
+                         ++s)
                         gather(s);
 #pragma unroll
                     for (int s = 4 * b; s < 4 * b + 4; ++s) {

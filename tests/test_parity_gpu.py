@@ -244,8 +244,8 @@ def test_zero_zones_is_a_no_op():
 def test_layout_info_one_factor_waves_and_placement():
     # the packing frees whole waves of second gathers and the placement lowers the modelled
     # gather cycles; the integrations above run through these layouts
-    cases = [("n150_r1604_arrhenius", 128, 0b10, 8), ("n365_r4400_arrhenius", 256, 0b1100, 16)]
-    for name, tpz, waves, f1 in cases:
+    cases = [("n150_r1604_arrhenius", 128, 0b10, 0, 32), ("n365_r4400_arrhenius", 256, 0b1100, 16, 56)]
+    for name, tpz, waves, f1, c2 in cases:
         net = binding.Network(workloads.preset(name, n_zones=1).network)
         try:
             info = net.layout_info(tpz)
@@ -255,6 +255,8 @@ def test_layout_info_one_factor_waves_and_placement():
             assert info["gather_cycles_placed"] < info["gather_cycles_packed"]
             # the two-factor rows sit in each lane's last slots; the leading ones run one-factor
             assert info["one_factor_slots"] >= f1 and info["one_factor_slots_run"] == f1
+            # balanced layout (150 species): the two-factor wave stops at slot 32 of 44
+            assert info["two_factor_wave_slots"] == c2
             with pytest.raises(binding.AsyError):
                 net.layout_info(96)
         finally:
