@@ -159,9 +159,9 @@ struct StratInstance {
 #define ASY_STRAT_F32_F1(W_, SPL_, C_, F1_)                                                     \
     {W_, SPL_, C_, C_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<C_, float>(), false, \
                                                false, float, C_, F1_>, F1_}
-#define ASY_STRAT_SPLIT(W_, SPL_, C_, CR_, C2_)                                                 \
+#define ASY_STRAT_SPLIT(W_, SPL_, C_, CR_, F1_, C2_)                                            \
     {W_, SPL_, C_, CR_, 0, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<CR_>(), false,    \
-                                                false, double, CR_, 0, C2_>, 0, C2_}
+                                                false, double, CR_, F1_, C2_>, F1_, C2_}
 #define ASY_STRAT_F32_SPLIT(W_, SPL_, C_, CR_, C2_)                                             \
     {W_, SPL_, C_, CR_, 4, integrate_strat_kernel<W_, SPL_, C_, strat_gather_ahead<CR_, float>(),   \
                                                 false, false, float, CR_, 0, C2_>, 0, C2_}
@@ -187,7 +187,7 @@ const StratInstance kStratInstances[] = {
     ASY_STRAT_F32(4, 2, 48), ASY_STRAT_F32(4, 2, 56), ASY_STRAT_F32(4, 2, 64), ASY_STRAT_F32(4, 2, 80),
     ASY_STRAT_F1(2, 2, 40, 40, 8), ASY_STRAT_F32_F1(2, 2, 40, 8),
     ASY_STRAT_F1(4, 2, 56, 40, 16), ASY_STRAT_F32_F1(4, 2, 56, 16),
-    ASY_STRAT_SPLIT(2, 2, 44, 40, 32), ASY_STRAT_F32_SPLIT(2, 2, 44, 40, 32),
+    ASY_STRAT_SPLIT(2, 2, 44, 40, 0, 32), ASY_STRAT_F32_SPLIT(2, 2, 44, 40, 32),
 };
 #undef ASY_STRAT
 #undef ASY_STRAT_CR
@@ -1303,8 +1303,12 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
             for (const auto &in : kStratInstances)
                 if (in.mode == 0 && in.C2 > 0 && in.W == W && in.SPL == L.SPL) {
                     build_strat(net, W, rows, split_above, &in);
-                    if (net->strat_bal[w_index(W)].ok)
+                    StratLayout &B = net->strat_bal[w_index(W)];
+                    if (B.ok && find_strat_instance(W, B.SPL, B.C, 0, B.f1, B.C2))
                         break;
+                    if (B.dev)
+                        (void)hipFree(B.dev);
+                    B = StratLayout{};
                 }
         }
     }
