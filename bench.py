@@ -537,8 +537,11 @@ def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3)) -> dict:
         parts = []
         for tol in tols:
             stride = max(1, int(round(12 * 1e-2 / tol)))  # about as many records per tolerance
-            tr = learned.generate_traces(net, tr_wl.zones, tol, stride=stride,
-                                         capacity=per_tol * 3)
+            # room for every record (about 230,000 per tolerance), so that which records are
+            # kept does not depend on the order in which zones finish
+            tr = learned.generate_traces(net, tr_wl.zones, tol, stride=stride, capacity=1 << 19)
+            if tr.taken > (1 << 19):
+                raise RuntimeError(f"trace buffer overflow at tol {tol}: {tr.taken} records")
             parts.append(learned.subsample(tr, per_tol, 4005))
         pairs = learned.augment_step_scale(learned.concat(parts), ev.network.n_species)
         tr_set, va_set = learned.split_by_zone(pairs, 0.1, 4005)
