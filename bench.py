@@ -345,6 +345,9 @@ def main(argv=None):
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposer comparison")
     ap.add_argument("--learned-zones", type=int, default=4096)
+    ap.add_argument("--mlp-train-probe", type=int, default=0,
+                    help="only time this many epochs of MLP training (batch 1024) on 64 seeded "
+                         "synthetic batches, for profiling the training kernels")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args(argv)
@@ -368,6 +371,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                           "launches": 3}), flush=True)
+        return 0
+    if args.mlp_train_probe:
+        print(json.dumps(mlp_train_probe(args.mlp_train_probe)), flush=True)
         return 0
     lds_measured = {w: binding.asy_probe_lds_bandwidth(w) / 1e9 for w in (8, 16)}
     peak = max(LDS_PEAK_GBS, *lds_measured.values())
@@ -440,6 +446,32 @@ def main(argv=None):
         log("cpu baseline done")
     print(json.dumps(out), flush=True)
     return 0
+
+
+def mlp_train_probe(epochs: int) -> dict:
+    """The learned leg's training loop (batch 1024, Adam) on 64 batches of seeded synthetic
+    features and labels, after one untimed warm-up epoch: device time per step and samples per
+    second."""
+    import numpy as np
+    import torch
+
+    from paper_1409_5826_amd import learned
+
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = 1024 * 64
+    x = torch.tensor(rng.uniform(-1.0, 1.0, (n, learned.N_FEATURES)), dtype=torch.float32,
+                     device="cuda")
+    y = torch.tensor(rng.normal(size=n), dtype=torch.float32, device="cuda")
+    tr = learned.Traces(x=x, y=y, zone=np.arange(n) // 1024, n_acc=np.zeros(n, np.int64), taken=n)
+    va = learned.Traces(x=x[:1024], y=y[:1024], zone=np.zeros(1024, np.int64),
+                        n_acc=np.zeros(1024, np.int64), taken=1024)
+    learned.train(tr, va, epochs=1, batch=1024, lr=1e-3, seed=5).mlp.close()  # warm-up: code loading
+    res = learned.train(tr, va, epochs=epochs, batch=1024, lr=1e-3, seed=5)
+    res.mlp.close()
+    steps = res.samples // 1024
+    return {"mlp_train_steps": steps, "batch": 1024, "seconds": res.seconds,
+            "us_per_step": res.seconds / steps * 1e6, "samples_per_s": res.samples / res.seconds,
+            "achieved_tflops": res.samples * MLP_FLOP_PER_SAMPLE / res.seconds / 1e12}
 
 
 def f32_leg(net, buf, Y0, dt0, stream, steps, b_step_fn, peak, autotune=True) -> dict:

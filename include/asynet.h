@@ -328,6 +328,16 @@ asy_status asy_mlp_train_step(asy_mlp *m, int32_t n, const float *x, const float
                               float *loss, void *stream);
 
 /*
+ * n_batches Adam steps in a row, step b on the samples [b batch, (b + 1) batch) of
+ * x (device [n_batches batch][ASY_MLP_N_IN]) and y (device [n_batches batch]); the
+ * same results as n_batches calls of asy_mlp_train_step, without the host's
+ * round trip per step.  losses (device [n_batches], may be NULL) receives each
+ * step's batch loss before its update.  1 <= batch <= batch_max, n_batches >= 0.
+ */
+asy_status asy_mlp_train_epoch(asy_mlp *m, int32_t n_batches, int32_t batch, const float *x,
+                               const float *y, float lr, float *losses, void *stream);
+
+/*
  * Batched inference through the same routine the integrator runs per zone
  * (one wave per sample, weights arranged for the matrix cores); o device [n].
  */

@@ -42,6 +42,7 @@ EXPORTS = (
     "asy_mlp_forward",
     "asy_mlp_gradient",
     "asy_mlp_train_step",
+    "asy_mlp_train_epoch",
     "asy_mlp_infer",
     "asy_set_mlp",
     "asy_integrate_batch_trace",
@@ -167,6 +168,7 @@ def lib():
         L.asy_mlp_forward.argtypes = [P, I32, P, P, P]
         L.asy_mlp_gradient.argtypes = [P, I32, P, P, P, P, P]
         L.asy_mlp_train_step.argtypes = [P, I32, P, P, F, P, P]
+        L.asy_mlp_train_epoch.argtypes = [P, I32, I32, P, P, F, P, P]
         L.asy_mlp_infer.argtypes = [P, I32, P, P, P]
         L.asy_set_mlp.argtypes = [P, P]
         L.asy_integrate_schedule.argtypes = [P, C.POINTER(asy_options), I32, I32, P, P, P, P, P, P,
@@ -176,7 +178,8 @@ def lib():
         L.asy_integrate_batch_trace.argtypes = [P, C.POINTER(asy_options), I32, P, P, P, P, P, P,
                                                 P, P, P, C.c_int64, P, I32, I32, P]
         for name in ("asy_mlp_create", "asy_mlp_set_params", "asy_mlp_get_params", "asy_mlp_forward",
-                     "asy_mlp_gradient", "asy_mlp_train_step", "asy_mlp_infer", "asy_set_mlp"):
+                     "asy_mlp_gradient", "asy_mlp_train_step", "asy_mlp_train_epoch", "asy_mlp_infer",
+                     "asy_set_mlp"):
             getattr(L, name).restype = I32
         _ = I64
         _lib = L
@@ -537,6 +540,22 @@ class Mlp:
         _check(lib().asy_mlp_train_step(self.handle, n, xp, yp, float(lr),
                                         None if loss is None else loss.data_ptr(),
                                         _stream_ptr(stream)), "asy_mlp_train_step")
+
+    def train_epoch(self, x, y, batch: int, lr=1e-3, losses=None, stream=None):
+        """x.shape[0] // batch Adam steps over consecutive batches of (x, y) in one call;
+        losses (device float32 [steps], optional) receives each step's loss."""
+        import torch
+
+        steps = int(x.shape[0]) // int(batch)
+        n = steps * int(batch)
+        xp = _dev_ptr(x[:n], torch.float32, (n, MLP_N_IN), "x")
+        yp = _dev_ptr(y[:n], torch.float32, (n,), "y")
+        lp = None
+        if losses is not None:
+            lp = _dev_ptr(losses, torch.float32, (steps,), "losses")
+        _check(lib().asy_mlp_train_epoch(self.handle, steps, int(batch), xp, yp, float(lr), lp,
+                                         _stream_ptr(stream)), "asy_mlp_train_epoch")
+        return steps
 
 
 def asy_set_mlp(net_handle, mlp: "Mlp"):

@@ -123,6 +123,7 @@ struct asy_mlp {
              *g_a1b = nullptr;
     float *a1 = nullptr, *a2 = nullptr, *out16 = nullptr, *o = nullptr, *g_o = nullptr,
           *g_a2 = nullptr, *g_a1 = nullptr;
+    float *colsum = nullptr;  // [kColsumBlocks][4][128] partial column sums
     int64_t t = 0;  // Adam steps taken
 };
 
@@ -1015,18 +1016,22 @@ hipError_t mlp_gradient_pass(asy_mlp *m, int n, const float *x, const float *y, 
                                  m->g_a1b, kMlpHid, nullptr, m->a1, kEpiReluGrad, kMlpHid, s);
     if (e != hipSuccess)
         return e;
-    // dW2 = h1b^T g_a2b, dW1 = xb^T g_a1b
-    e = launch_gemm<true, false>(kMlpHid, kMlpHid, B, m->h1b, kMlpHid, m->g_a2b, kMlpHid,
-                                 m->g + kOffW2, nullptr, kMlpHid, nullptr, nullptr, kEpiStore, kMlpHid, s);
+    // dW2 = h1b^T g_a2b, dW1 = xb^T g_a1b (the batch split over the waves of a tile)
+    hipLaunchKernelGGL(gemm_bf16_wgrad_kernel, dim3((kMlpHid / 16) * (kMlpHid / 16)), dim3(256), 0,
+                       s, kMlpHid, kMlpHid, B, m->h1b, kMlpHid, m->g_a2b, kMlpHid, m->g + kOffW2,
+                       kMlpHid);
+    hipLaunchKernelGGL(gemm_bf16_wgrad_kernel, dim3((kMlpInPad / 16) * (kMlpHid / 16)), dim3(256),
+                       0, s, kMlpInPad, kMlpHid, B, m->xb, kMlpInPad, m->g_a1b, kMlpHid,
+                       m->g + kOffW1, kMlpHid);
+    e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    e = launch_gemm<true, false>(kMlpInPad, kMlpHid, B, m->xb, kMlpInPad, m->g_a1b, kMlpHid,
-                                 m->g + kOffW1, nullptr, kMlpHid, nullptr, nullptr, kEpiStore, kMlpHid, s);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(kColsumGroups * kMlpHid), 0, s, B, m->g_a1,
-                       m->g_a2, m->g_o,
-                       m->h2b, m->g_ob, m->g);
+    // bias gradients and the output layer's weight gradient: column sums over the batch
+    const int rows_per = (B + kColsumBlocks - 1) / kColsumBlocks;
+    hipLaunchKernelGGL(mlp_colsum_part_kernel, dim3(kColsumBlocks), dim3(kColsumGroups * kMlpHid),
+                       0, s, B, rows_per, m->g_a1, m->g_a2, m->g_o, m->h2b, m->g_ob, m->colsum);
+    hipLaunchKernelGGL(mlp_colsum_final_kernel, dim3(1), dim3(kMlpHid), 0, s, kColsumBlocks,
+                       m->colsum, m->g);
     return hipGetLastError();
 }
 
@@ -1808,6 +1813,7 @@ asy_status asy_mlp_create(int32_t batch_max, asy_mlp **out)
     const size_t o_a1 = carve(B * kMlpHid * 4), o_a2 = carve(B * kMlpHid * 4), o_o16 = carve(B * 16 * 4);
     const size_t o_o = carve(B * 4), o_go = carve(B * 4), o_ga2 = carve(B * kMlpHid * 4);
     const size_t o_ga1 = carve(B * kMlpHid * 4);
+    const size_t o_cs = carve((size_t)kColsumBlocks * 4 * kMlpHid * 4);
     hipError_t e = hipMalloc(&m->block, off);
     if (e != hipSuccess) {
         delete m;
@@ -1828,6 +1834,7 @@ asy_status asy_mlp_create(int32_t batch_max, asy_mlp **out)
     m->g_a1b = H(o_ga1b);
     m->a1 = F(o_a1); m->a2 = F(o_a2); m->out16 = F(o_o16); m->o = F(o_o); m->g_o = F(o_go);
     m->g_a2 = F(o_ga2); m->g_a1 = F(o_ga1);
+    m->colsum = F(o_cs);
     *out = m;
     return ASY_OK;
 }
@@ -1914,6 +1921,33 @@ asy_status asy_mlp_train_step(asy_mlp *m, int32_t n, const float *x, const float
     hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->m, m->v, lr,
                        (float)beta1, (float)beta2, 1e-8f, c1, c2);
     HIP_TRY(hipGetLastError());
+    return ASY_OK;
+}
+
+asy_status asy_mlp_train_epoch(asy_mlp *m, int32_t n_batches, int32_t batch, const float *x,
+                               const float *y, float lr, float *losses, void *stream)
+{
+    g_last_error.clear();
+    if (n_batches < 0)
+        return fail(ASY_EINVAL, "n_batches must be >= 0");
+    asy_status st = mlp_check(m, batch, x);
+    if (st != ASY_OK)
+        return st;
+    if (!y || !(lr > 0.0f) || !std::isfinite(lr))
+        return fail(ASY_EINVAL, "y must be non-NULL and lr finite and > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double beta1 = 0.9, beta2 = 0.999;
+    for (int32_t b = 0; b < n_batches; ++b) {
+        const size_t first = (size_t)b * (size_t)batch;
+        HIP_TRY(mlp_gradient_pass(m, batch, x + first * kMlpIn, y + first,
+                                  losses ? losses + b : nullptr, s));
+        m->t += 1;
+        const float c1 = (float)(1.0 - std::pow(beta1, (double)m->t));
+        const float c2 = (float)(1.0 - std::pow(beta2, (double)m->t));
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->m, m->v, lr,
+                           (float)beta1, (float)beta2, 1e-8f, c1, c2);
+        HIP_TRY(hipGetLastError());
+    }
     return ASY_OK;
 }
 

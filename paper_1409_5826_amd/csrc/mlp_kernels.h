@@ -128,6 +128,49 @@ gemm_bf16_kernel(int M, int N, int K, const uint16_t *A, int lda, const uint16_t
     }
 }
 
+// Weight gradients C[M][N] = A^T[M][K] B[K][N] (A stored [K][M], B [K][N], bfloat16 bits,
+// K = the batch, a multiple of 32): one 16x16 tile per workgroup of 4 waves.  Wave w multiplies
+// the k-steps of 32 with index w, w + 4, w + 8, ... into its own accumulator; the four are added
+// in wave order through LDS -- a fixed order, so the result is deterministic -- and stored.  The
+// batch dimension is long and the tiles few (96 and 64), so splitting it is what fills the chip.
+__global__ void __launch_bounds__(256)
+gemm_bf16_wgrad_kernel(int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
+                       float *C, int ldc)
+{
+    __shared__ float red[4][16][16];
+    const int lane = threadIdx.x % 64;
+    const int wave = threadIdx.x / 64;
+    const int tiles_n = N / 16;
+    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    const int m = tm * 16 + lane % 16;
+    const int n = tn * 16 + lane % 16;
+    const int kg = (lane / 16) * 8;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 32 * wave; k0 < K; k0 += 128) {
+        uint16_t a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + kg + e;
+            a[e] = A[(size_t)k * lda + m];
+            b[e] = B[(size_t)k * ldb + n];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pack_bf16x8(a), pack_bf16x8(b), acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        red[wave][(lane / 16) * 4 + e][lane % 16] = acc[e];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = (lane / 16) * 4 + e;
+            const float v = ((red[0][r][lane % 16] + red[1][r][lane % 16]) + red[2][r][lane % 16]) +
+                            red[3][r][lane % 16];
+            C[(size_t)(tm * 16 + r) * ldc + n] = v;
+        }
+    }
+}
+
 // x [n][166] FP32 -> xb [n_pad][192] bf16 bits; padding columns and rows n..n_pad-1 are zero
 __global__ void mlp_pack_input_kernel(int n, int n_pad, const float *x, uint16_t *xb)
 {
@@ -212,54 +255,73 @@ __global__ void mlp_out_grad_kernel(int n, const uint16_t *g_ob, const uint16_t 
 }
 
 // dW3[j] = sum_b h2b[b][j] g_ob[b] and the bias gradients (column sums), FP32.
-// One workgroup of kColsumGroups x 128 threads: thread (g, j) sums rows
-// b = g, g + kColsumGroups, ... of column j (coalesced across j), then the
-// group partials are added in group order -- a fixed order, so the result is
-// deterministic.  b3's gradient is a sum over the batch reduced the same way.
+// Column sums over the batch (the bias gradients, the output layer's weight gradient and b3's
+// gradient) in two kernels.  Workgroup q of mlp_colsum_part_kernel (kColsumGroups x 128
+// threads) takes the rows [q rows_per, (q + 1) rows_per): thread (g, j) sums rows r0 + g,
+// r0 + g + kColsumGroups, ... of column j (coalesced across j), the group partials are added in
+// group order, and the workgroup writes part[q][4][128] (b1, b2, W3 columns; b3 in [3][0]).
+// mlp_colsum_final_kernel adds the workgroups' partials in workgroup order.  Every order is
+// fixed, so the result is deterministic.
 constexpr int kColsumGroups = 8;
+constexpr int kColsumBlocks = 16;
 
 __global__ void __launch_bounds__(kColsumGroups * kMlpHid)
-mlp_colsum_kernel(int n, const float *g_a1, const float *g_a2, const float *g_o,
-                  const uint16_t *h2b, const uint16_t *g_ob, float *grad)
+mlp_colsum_part_kernel(int n, int rows_per, const float *g_a1, const float *g_a2, const float *g_o,
+                       const uint16_t *h2b, const uint16_t *g_ob, float *part)
 {
-    __shared__ float part[4][kColsumGroups][kMlpHid];
+    __shared__ float grp[4][kColsumGroups][kMlpHid];
     const int j = threadIdx.x % kMlpHid;
     const int g = threadIdx.x / kMlpHid;
+    const int r0 = blockIdx.x * rows_per;
+    const int r1 = min(n, r0 + rows_per);
     float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, s4 = 0.0f;
-#pragma unroll 4
-    for (int b = g; b < n; b += kColsumGroups) {
+    for (int b = r0 + g; b < r1; b += kColsumGroups) {
         const size_t at = (size_t)b * kMlpHid + j;
         const float go = bf16_bits_to_f32(g_ob[b]);
         s1 += g_a1[at];
         s2 += g_a2[at];
         s3 += bf16_bits_to_f32(h2b[at]) * go;
+        if (j == 0)
+            s4 += g_o[b];
     }
-    // b3: column j of a [n / 128 + 1][128] view of g_o
-    for (int b = g * kMlpHid + j; b < n; b += kColsumGroups * kMlpHid)
-        s4 += g_o[b];
-    part[0][g][j] = s1;
-    part[1][g][j] = s2;
-    part[2][g][j] = s3;
-    part[3][g][j] = s4;
+    grp[0][g][j] = s1;
+    grp[1][g][j] = s2;
+    grp[2][g][j] = s3;
+    grp[3][g][j] = s4;
     __syncthreads();
     if (g == 0) {
-        float t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
+        float t1 = 0.0f, t2 = 0.0f, t3 = 0.0f, t4 = 0.0f;
         for (int q = 0; q < kColsumGroups; ++q) {
-            t1 += part[0][q][j];
-            t2 += part[1][q][j];
-            t3 += part[2][q][j];
+            t1 += grp[0][q][j];
+            t2 += grp[1][q][j];
+            t3 += grp[2][q][j];
+            t4 += grp[3][q][j];
         }
-        grad[kOffB1 + j] = t1;
-        grad[kOffB2 + j] = t2;
-        grad[kOffW3 + j] = t3;
+        float *out = part + (size_t)blockIdx.x * 4 * kMlpHid;
+        out[j] = t1;
+        out[kMlpHid + j] = t2;
+        out[2 * kMlpHid + j] = t3;
+        out[3 * kMlpHid + j] = t4;  // only column 0 carries b3's partial
     }
-    if (threadIdx.x == 0) {
-        float t = 0.0f;
-        for (int q = 0; q < kColsumGroups; ++q)
-            for (int c = 0; c < kMlpHid; ++c)
-                t += part[3][q][c];
-        grad[kOffB3] = t;
+}
+
+__global__ void __launch_bounds__(kMlpHid)
+mlp_colsum_final_kernel(int blocks, const float *part, float *grad)
+{
+    const int j = threadIdx.x;
+    float t1 = 0.0f, t2 = 0.0f, t3 = 0.0f, t4 = 0.0f;
+    for (int q = 0; q < blocks; ++q) {
+        const float *in = part + (size_t)q * 4 * kMlpHid;
+        t1 += in[j];
+        t2 += in[kMlpHid + j];
+        t3 += in[2 * kMlpHid + j];
+        t4 += in[3 * kMlpHid];
     }
+    grad[kOffB1 + j] = t1;
+    grad[kOffB2 + j] = t2;
+    grad[kOffW3 + j] = t3;
+    if (j == 0)
+        grad[kOffB3] = t4;
 }
 
 // Adam on the FP32 masters; c1 = 1 - beta1^t, c2 = 1 - beta2^t

@@ -172,17 +172,13 @@ def train(train_set: Traces, val_set: Traces, epochs: int = 20, batch: int = 102
     res.baseline_val_loss = float(((yv - y_mean) ** 2).mean().item())
     n = int(train_set.x.shape[0])
     rng = np.random.Generator(np.random.PCG64(seed))
-    loss_dev = torch.zeros(1, dtype=torch.float32, device="cuda")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for _ in range(epochs):
         perm = torch.as_tensor(rng.permutation(n), device=train_set.x.device)
         xs, ys = train_set.x.index_select(0, perm), train_set.y.index_select(0, perm)
         losses = torch.zeros(n // batch, dtype=torch.float32, device="cuda")
         ev0.record()
-        for b in range(n // batch):
-            mlp.train_step(xs[b * batch:(b + 1) * batch], ys[b * batch:(b + 1) * batch], lr=lr,
-                           loss=loss_dev)
-            losses[b:b + 1].copy_(loss_dev)
+        mlp.train_epoch(xs, ys, batch, lr=lr, losses=losses)  # n // batch steps, one call
         ev1.record()
         torch.cuda.synchronize()
         res.seconds += ev0.elapsed_time(ev1) / 1e3
