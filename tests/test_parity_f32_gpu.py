@@ -89,6 +89,8 @@ def test_arrhenius_full_size_every_zone(name):
     exact = compare(g, ref)
     say(f"  bit-exact zones {exact:.3f}")
     assert (g["zone_status"] == binding.ZONE_OK).all()
+    for key, gkey in (("Y", "Y"), ("dt", "dt"), ("n_acc", "n_accepted"), ("n_rej", "n_rejected")):
+        np.testing.assert_array_equal(g[gkey], ref[key], err_msg=key)
 
 
 def test_placement_invariance_f32():

@@ -112,6 +112,9 @@ def test_arrhenius_full_size_every_zone(name):
         f"{np.mean(g['n_accepted'] == ref['n_acc']):.4f} of zones")
     assert (g["zone_status"] == binding.ZONE_OK).all()
     assert (g["Y"] >= 0).all()
+    # the rates' exponential is one algorithm on both sides, so every zone is identical
+    for key, gkey in (("Y", "Y"), ("dt", "dt"), ("n_acc", "n_accepted"), ("n_rej", "n_rejected")):
+        np.testing.assert_array_equal(g[gkey], ref[key], err_msg=key)
 
 
 def test_arrhenius_small_batch_all_zones():
