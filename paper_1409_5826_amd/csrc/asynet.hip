@@ -633,8 +633,8 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         sn.feat = sn.rlds + spill_slots * lanes * B;
         sn.end_mask = end_mask;
         sn.one_waves = one_waves;
-        // single precision: a lane's second and later Y cells start at the first one-factor wave
-        sn.rot = (p == 1 && one_waves) ? (lanes - 64 * __builtin_ctz(one_waves)) % lanes : 0;
+        // a lane's second and later Y cells start at the first one-factor wave
+        sn.rot = one_waves ? (lanes - 64 * __builtin_ctz(one_waves)) % lanes : 0;
         sn.desc = reinterpret_cast<const uint32_t *>(base + o_desc[p]);
         sn.rx = reinterpret_cast<const int32_t *>(base + o_rx);
         sn.cell_species = reinterpret_cast<const int32_t *>(base + o_cspec);

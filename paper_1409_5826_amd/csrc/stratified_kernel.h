@@ -294,14 +294,10 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     float &xw_o = *reinterpret_cast<float *>(xb + 84);
     float *feat = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + sn.feat);
     float *hs = feat + kMlpInPad;  // [2 * kMlpHid]
-    // Y cells of the lane: zl + m * lanes; in single precision m * lanes + ((zl + rot) mod lanes)
-    // for m > 0, so that the cells past the first lanes-many go first to the one-factor waves
-    // (the lighter ones; measured faster in single precision, slower in double)
+    // Y cells of the lane: zl, then m * lanes + ((zl + rot) mod lanes) for m > 0, so that the
+    // cells past the first lanes-many go first to the one-factor waves (measured faster)
     auto cell_at = [&](int m) {
-        if constexpr (sizeof(T) == 4)
-            return m == 0 ? zl : m * LANES + ((zl + sn.rot) & (LANES - 1));
-        else
-            return zl + m * LANES;
+        return m == 0 ? zl : m * LANES + ((zl + sn.rot) & (LANES - 1));
     };
     // the lane's first row-sum cell; its species' F+ / k cells, read from LDS where
     // needed (held in registers across the step loop they would spill), lane-major
