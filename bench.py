@@ -180,13 +180,14 @@ def run_workload(name, steps, warmup, peak, launch=None, autotune=True, n_zones=
     cfg = net.get_launch()
     b_step = algorithmic_bytes_per_zone_step(n.n_species, n.n_reactions, n.n_destruction, 8,
                                              cfg["variant"] == 1)
-    ms = float(np.mean(launch_ms))
+    ms = float(np.median(launch_ms))  # median of the timed launches
     achieved = b_step * att / (ms / 1e3) / 1e9
     summary = {
         "workload": wl.name, "description": wl.description, "zones": wl.zones.n_zones,
         "n_species": n.n_species, "n_reactions": n.n_reactions, "tol": wl.tol,
         "wall_s": elapsed, "time_to_t_end_ms": ms,
         "time_to_t_end_ms_min": float(np.min(launch_ms)),
+        "time_to_t_end_ms_mean": float(np.mean(launch_ms)),
         "zone_steps_per_s": acc / (ms / 1e3), "attempted_steps_per_s": att / (ms / 1e3),
         "accepted_zone_steps": acc, "rejected_zone_steps": att - acc,
         "bytes_per_zone_step": b_step, "achieved_GBs": achieved, "frac": achieved / peak,
