@@ -41,6 +41,8 @@ def test_time_at_equal_error_interpolates_log_log():
     assert err == 0.2
     assert abs(ms_p - 500.0) < 1e-9 and abs(ms_l - 5000.0) < 1e-9
     assert bench.time_at_equal_error([(1.0, 1.0), (0.5, 2.0)], [(0.1, 5.0), (0.05, 9.0)]) is None
+    # a form whose every tolerance left a reference zone unfinished has no curve
+    assert bench.time_at_equal_error([(1.0, 1.0)], []) is None
 
 
 def test_mass_drift_reports_the_weighted_sum_ratio():
