@@ -56,3 +56,35 @@ def test_weighted_sum_conserved_on_a_stiff_network():
     w = net.weight.astype(float)
     assert abs(w @ Y - w @ z.Y0[0]) <= 1e-9 * (w @ z.Y0[0])
     assert (Y > -1e-12).all()
+
+
+def test_committed_c5_reference_is_consistent():
+    """The stored reference (tests/golden/c5_radau_reference.json): one row per listed zone,
+    finite and non-negative to the absolute tolerance, Σ w Y(t_end) equal to Σ w Y(0) (a linear invariant of Eq. eq1.1
+    that Radau keeps to its tolerance), and the fastest zone re-solved by the generator's own
+    call reproduces its row within the stored error estimate."""
+    import json
+    import os
+    import time
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "c5_radau_reference.json")
+    with open(path) as fh:
+        ref = json.load(fh)
+    wl = workloads.preset(ref["workload"], n_zones=ref["n_zones_total"],
+                          seed_offset=ref["seed_offset"])
+    zones = np.asarray(ref["zones"])
+    Y = np.asarray(ref["Y"])
+    assert Y.shape == (len(zones), wl.network.n_species) and len(zones) >= 256
+    # Radau keeps abundances non-negative only to its absolute tolerance
+    assert np.isfinite(Y).all() and (Y >= -10 * ref["atol"]).all()
+    w = wl.network.weight.astype(np.float64)
+    m0 = wl.zones.Y0[zones] @ w
+    assert np.abs(Y @ w - m0).max() <= 1e-7 * m0.max()
+    # zone 0 and 3 were also solved 10x tighter; re-solve one zone here (a few seconds)
+    z = 128
+    t0 = time.perf_counter()
+    Yz, _, _ = ode_reference.radau(wl.network, wl.zones.k[z], wl.zones.Y0[z], wl.zones.t_end[z],
+                                   rtol=ref["rtol"], atol=ref["atol"])
+    assert time.perf_counter() - t0 < 120
+    assert w @ np.abs(Yz - Y[list(zones).index(z)]) <= max(ref["error_estimate_mass_fraction_l1"],
+                                                           1e-12)

@@ -85,10 +85,14 @@ def test_pins_catch_mutation(name, tmp_path):
         head = head.replace(before, after)
     (dst / "oracle.c").write_text(head + tail)
     env = dict(os.environ, PYTHONPATH=f"{tmp_path}{os.pathsep}{ROOT}")
+    # every pin file runs; the one a mutation of its kind most likely fails goes first (-x)
+    files = ["test_oracle_pins.py", "test_mlp_oracle.py", "test_oracle_f32.py"]
+    first = ("test_oracle_f32.py" if name.startswith("f32_") else
+             "test_mlp_oracle.py" if learned else "test_oracle_pins.py")
+    files.remove(first)
+    files.insert(0, first)
     res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                          os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                          os.path.join(ROOT, "tests", "test_mlp_oracle.py"),
-                          os.path.join(ROOT, "tests", "test_oracle_f32.py")],
+                          *[os.path.join(ROOT, "tests", f) for f in files]],
                          env=env, cwd=str(tmp_path), capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"no pin failed for mutation {name}:\n{res.stdout[-2000:]}"
     # and the copy really was the one under test
