@@ -547,6 +547,8 @@ class Mlp:
         import torch
 
         steps = int(x.shape[0]) // int(batch)
+        if steps == 0:
+            return 0
         n = steps * int(batch)
         xp = _dev_ptr(x[:n], torch.float32, (n, MLP_N_IN), "x")
         yp = _dev_ptr(y[:n], torch.float32, (n,), "y")
