@@ -657,6 +657,22 @@ size_t lds_bytes_variant0(const asy_network *net)
 
 // LDS of one workgroup of variant 1: mode 4 (single precision) has float cells;
 // modes 1-3 (traces, learned controller) add the network's input and hidden layers.
+// Modelled cost of the slower kind of wave of a layout per step, in units of a one-factor slot:
+// a two-factor slot costs 1.45 (second gather and product; measured per-slot phase times of the
+// two kinds of wave, 93 and 65 cycles), a rate read from LDS (slots >= CR) 0.3.
+double modeled_wave_cost(const StratLayout &L, const StratInstance &in)
+{
+    const int all = (1 << L.W) - 1;
+    const int c2 = in.C2 > 0 ? in.C2 : in.C;
+    auto lds_rates = [&](int slots) { return 0.3 * std::max(0, slots - in.CR); };
+    double cost = 0.0;
+    if ((int)L.one_waves != all)  // waves with two-factor terms
+        cost = std::max(cost, in.F1 + 1.45 * (c2 - in.F1) + lds_rates(c2));
+    if (L.one_waves)              // one-factor waves
+        cost = std::max(cost, in.C + lds_rates(in.C));
+    return cost;
+}
+
 // The layout a kernel family runs with W waves per zone: the balanced layout for the plain
 // controller (double or single precision) where it was built and an instance exists, else the
 // default layout, which every family can run.
@@ -1305,11 +1321,17 @@ asy_status asy_network_create(const asy_network_desc *d, asy_network **out)
             const StratLayout &L = net->strat[w_index(W)];
             if (!L.ok || !L.one_waves)
                 continue;
+            const StratInstance *din = find_strat_instance(W, L.SPL, L.C, 0, L.f1);
+            if (!din)
+                continue;
             for (const auto &in : kStratInstances)
                 if (in.mode == 0 && in.C2 > 0 && in.W == W && in.SPL == L.SPL) {
                     build_strat(net, W, rows, split_above, &in);
                     StratLayout &B = net->strat_bal[w_index(W)];
-                    if (B.ok && find_strat_instance(W, B.SPL, B.C, 0, B.f1, B.C2))
+                    const StratInstance *bin =
+                        B.ok ? find_strat_instance(W, B.SPL, B.C, 0, B.f1, B.C2) : nullptr;
+                    // kept only where the model expects it to be faster than the default layout
+                    if (bin && modeled_wave_cost(B, *bin) < modeled_wave_cost(L, *din))
                         break;
                     if (B.dev)
                         (void)hipFree(B.dev);
