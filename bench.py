@@ -543,7 +543,7 @@ def time_at_equal_error(curve_a, curve_b):
     return lo, interp(curve_a, lo), interp(curve_b, lo)
 
 
-def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3)) -> dict:
+def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3), tight_tols=(3e-4, 1e-4)) -> dict:
     """The learned step proposer against the plain controller on held-out zones of the
     150-species constant-rate distribution.
 
@@ -552,7 +552,8 @@ def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3)) -> dict:
     20 epochs on the device.  Evaluation: both forms on n_eval_zones held-out
     zones at each tolerance; time to t_end of the whole batch; final-abundance error
     (mass-fraction L1) on the zones of the committed Radau reference; the time ratio at
-    equal error interpolated from the two error-vs-time curves."""
+    equal error interpolated from the two error-vs-time curves.  The plain form also runs at
+    tight_tols, and the slope of its error against tol gives the tol a 1e-6 error would need."""
     import json as _json
 
     import numpy as np
@@ -620,6 +621,24 @@ def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3)) -> dict:
             row["time_ratio_learned_over_plain"] = row["learned"]["ms"] / row["plain"]["ms"]
             rows.append(row)
         eq = time_at_equal_error(curves["plain"], curves["learned"])
+        # the plain form alone at tighter tolerances: how its error falls toward the 1e-6 target
+        tight = []
+        for tol in tight_tols:
+            r = learned.integrate(net, ev.zones, tol, False, repeats=1)
+            done = r.status[ref_idx] == binding.ZONE_OK
+            err = np.where(done, learned.mass_error(r.Y[ref_idx], ref_Y, w), np.inf)
+            tight.append({"tol": tol, "ms": r.ms, "accepted_per_zone": float(r.n_acc.mean()),
+                          "err_median": float(np.median(err))})
+            log(f"learned: plain at tol {tol:g} {r.ms:.0f} ms, median error {np.median(err):.3g}")
+        pts = [(row["tol"], row["plain"]["err_median"]) for row in rows] + \
+              [(t["tol"], t["err_median"]) for t in tight]
+        pts = [(t, e) for t, e in pts if e is not None and np.isfinite(e) and e > 0]
+        order = tol_for_target = None
+        if len(pts) >= 2:
+            # least-squares slope of log error against log tol, and the tol it implies for 1e-6
+            lt, le = np.log10([p[0] for p in pts]), np.log10([p[1] for p in pts])
+            order, icpt = np.polyfit(lt, le, 1)
+            tol_for_target = float(10.0 ** ((-6.0 - icpt) / order))
         sps = res.samples / res.seconds if res.seconds > 0 else None
         out = {
             "workload": f"{ev.name} held-out zones (seed offset {ref['seed_offset']}), "
@@ -644,6 +663,9 @@ def learned_leg(n_eval_zones: int, tols=(1e-2, 3e-3, 1e-3)) -> dict:
                 "time_ratio_learned_over_plain": eq[2] / eq[1]},
             "target_err_1e-6_reached": bool(any(p[0] <= 1e-6 for p in curves["plain"] +
                                                 curves["learned"])),
+            "plain_tight_tols": tight,
+            "plain_error_order_in_tol": None if order is None else float(order),
+            "plain_tol_for_err_1e-6_extrapolated": tol_for_target,
             "plain_mass_drift": drift,
         }
         res.mlp.close()
