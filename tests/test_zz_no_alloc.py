@@ -28,11 +28,11 @@ def say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _run(net, zones, noalloc):
+def _run(net, zones, noalloc, opts=None):
     import torch
 
     buf = net.zone_buffers(zones)
-    net.integrate(buf, noalloc=noalloc)
+    net.integrate(buf, opts, noalloc=noalloc)
     torch.cuda.synchronize()
     return {k: buf[k].cpu().numpy() for k in FIELDS}
 
@@ -60,6 +60,23 @@ def test_noalloc_matches_batch_on_two_calls(name, n1, n2, launch):
         for zones in (wl.zones, second):
             want = _run(net, zones, noalloc=False)
             got = _run(net, zones, noalloc=True)
+            _same(got, want)
+            assert (got["zone_status"] == binding.ZONE_OK).all()
+    finally:
+        net.close()
+
+
+def test_noalloc_single_precision_on_two_calls():
+    """The single-precision kernels through the entry point that allocates nothing."""
+    wl = workloads.preset("n150_r1604_arrhenius", n_zones=160)
+    say("case f32 n150_r1604_arrhenius zones=160 then 48")
+    net = binding.Network(wl.network)
+    try:
+        opts = binding.options_default(precision=binding.PREC_F32)
+        second = wl.zones.subset(np.arange(100, 148))
+        for zones in (wl.zones, second):
+            want = _run(net, zones, noalloc=False, opts=opts)
+            got = _run(net, zones, noalloc=True, opts=opts)
             _same(got, want)
             assert (got["zone_status"] == binding.ZONE_OK).all()
     finally:
