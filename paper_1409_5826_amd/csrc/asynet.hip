@@ -337,8 +337,8 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     L.C_needed = C_needed;
     L.SPL = (N + lanes - 1) / lanes;
     const StratInstance *inst = bal ? bal : find_strat_instance(W, L.SPL, C_needed);
-    if (!inst || C_needed > 256 || inst->SPL != L.SPL || inst->W != W)
-        return;  // end_mask holds at most 64 blocks of 4 slots
+    if (!inst || inst->SPL != L.SPL || inst->W != W)
+        return;
     const int C = inst->C;
     L.C = C;
     L.C2 = bal ? bal->C2 : 0;
@@ -517,7 +517,6 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
     std::vector<int32_t> rx((size_t)C * lanes, -1), split_first(1, 0);
     for (const auto &ch : split_chunks)
         split_first.push_back(split_first.back() + (int32_t)ch.size());
-    uint64_t end_mask = 0;
     for (int p = 0; p < 2; ++p) {
         const uint32_t B = p == 0 ? 8u : 4u;
         // padding terms read ONE twice and carry a zero rate
@@ -537,7 +536,6 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
                 start += padded(row);
                 const int blk = start / 4 - 1;  // the row ends in this block
                 desc[p][desc_index(4 * blk, l, lanes)] |= 0x80000000u;
-                end_mask |= 1ull << blk;
             }
             lane_out[p].push_back((uint32_t)lane_first[l] * B);
         }
@@ -631,7 +629,6 @@ void build_strat(asy_network *net, int W, const std::vector<std::vector<Term>> &
         const int spill_slots = pi ? pi->C - pi->CR : 0;
         sn.rlds = sn.tab + ((L.SPL * lanes + n_split + 1 + split_first.back()) * 4 + 15) / 16 * 16;
         sn.feat = sn.rlds + spill_slots * lanes * B;
-        sn.end_mask = end_mask;
         sn.one_waves = one_waves;
         // a lane's second and later Y cells start at the first one-factor wave
         sn.rot = one_waves ? (lanes - 64 * __builtin_ctz(one_waves)) % lanes : 0;

@@ -21,8 +21,10 @@
 // the end of a block of 4 slots, at a different block on each lane.  The sums land in the LDS cells after Y in lane order -- lane l's k-th
 // row in cell lane_out[l] + k -- so a lane needs only one bit per block, set
 // in the first descriptor of the block where one of its rows ends, and a
-// running cell address; a uniform mask (end_mask, bit b: some lane ends a row
-// in block b) skips the test in the other blocks.  Each species' update reads
+// running cell address (a block-wide mask of the blocks where some lane ends a
+// row would skip the test elsewhere, but the compiler keeps it as one scalar
+// register pair per block, which spills scalars at 44 slots and more, and at
+// these sizes nearly every block ends a row on some lane).  Each species' update reads
 // its two sums through a per-species pair of cell addresses.
 // The zone's rates are loaded once into registers (slot s of the lane holds
 // the rate of its term s), so per step the only random LDS traffic is the
@@ -53,7 +55,6 @@ struct StratNetwork {
     int32_t rlds;              // LDS byte address of the rates of slots >= CR (instances that
                                // keep only CR slots' rates in registers): [C - CR][lanes] of T
     int32_t feat;              // LDS byte address of the learned controller's input and layers
-    uint64_t end_mask;         // bit b: some lane ends a row in block b (slots 4b..4b+3)
     int32_t rot;               // rotation of the lanes' second and later Y cells
     uint32_t one_waves;        // bit w: every term of wave w has the 1.0 cell as second factor
                                // (no second gathers, no multiplies by 1.0)
@@ -282,7 +283,7 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
     const int N = sn.n_species;
     const int R = sn.n_reactions;
     const int tid = threadIdx.x;
-    const int wave = tid / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // uniform: scalar addresses
     const int lane = tid % kWave;
     const int zl = tid;  // lane within the zone
     T *Y = reinterpret_cast<T *>(lds);
@@ -417,7 +418,6 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             for (int c = zl; c < kMlpInPad; c += 64 * W)
                 feat[c] = 0.0f;
         }
-        const uint64_t emask = sn.end_mask;
         // every term of this wave has the 1.0 cell as second factor (a uniform value)
         const bool one_wave = (sn.one_waves >> __builtin_amdgcn_readfirstlane(wave)) & 1u;
         constexpr int NB = C / 4;
@@ -426,21 +426,26 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
         constexpr int kDescAhead = C <= 44 ? 4 : 3;
         constexpr int kGatherAhead = GA; // abundance-gather distance, in blocks
         uint32_t dq[C];
-        const uint4 *dsc;
+        // The descriptors are read through a buffer resource: the lane's byte offset is one
+        // register for the whole zone and a block's offset is a scalar, so a load costs no
+        // vector address arithmetic (a 64-bit pointer per block costs two adds per load).
+        const __amdgpu_buffer_rsrc_t dsc_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint32_t *>(sn.desc), (short)0, C * LANES * 4, 0x00020000);
+        const int dsc_lane = zl * 16;
+        int dsc_base = 0;
         // the descriptors of block b (one 16-byte load per lane)
         auto load_block = [&](int b) {
-            const uint4 v = dsc[b * LANES];
-            dq[4 * b] = v.x;
-            dq[4 * b + 1] = v.y;
-            dq[4 * b + 2] = v.z;
-            dq[4 * b + 3] = v.w;
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(dsc_rsrc, dsc_lane,
+                                                                 dsc_base + b * LANES * 16, 0);
+            dq[4 * b] = v[0];
+            dq[4 * b + 1] = v[1];
+            dq[4 * b + 2] = v[2];
+            dq[4 * b + 3] = v[3];
         };
         {
-            int doff = 0;
             // opaque offset: the descriptor loads stay inside the step loop
             // instead of being hoisted into registers for the whole zone
-            asm volatile("" : "+s"(doff));
-            dsc = reinterpret_cast<const uint4 *>(sn.desc) + doff + zl;
+            asm volatile("" : "+s"(dsc_base));
 #pragma unroll
             for (int b = 0; b < kDescAhead && b < NB; ++b)
                 load_block(b);
@@ -458,10 +463,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
             const double h = clipped ? t_end - t : step;
 
             // Creation fluxes and depletion rates: the lane's packed rows.
-            // Rows end on multiples of 4 slots; blocks where some lane ends a
-            // row are flagged in end_mask, a uniform kernel argument, so the
-            // test is a scalar bit test on a compile-time block index, and in
-            // a flagged block the lane's own test is the sign of a descriptor.
+            // Rows end on multiples of 4 slots; a lane's test at the end of a
+            // block is the sign of the block's first descriptor.
             // Software pipeline: while block b is summed, the gathers of blocks
             // up to b+kGatherAhead and the descriptors of block b+kDescAhead are
             // in flight; the first kDescAhead blocks' descriptors of a step are
@@ -501,12 +504,10 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                         else
                             acc = acc + (rate_of(s) * gx[s]) * gy[s];
                     }
-                    if ((emask >> b) & 1u) {
-                        if ((int32_t)dq[4 * b] < 0) {
-                            lds_st<T>(wp, acc);
-                            wp += sizeof(T);
-                            acc = (T)0.0;
-                        }
+                    if ((int32_t)dq[4 * b] < 0) {
+                        lds_st<T>(wp, acc);
+                        wp += sizeof(T);
+                        acc = (T)0.0;
                     }
                 }
             };
@@ -516,9 +517,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                 slot_phase(BoolTag<false>{});
             // descriptors of the first blocks of the next step
             {
-                int doff = 0;
-                asm volatile("" : "+s"(doff));
-                dsc = reinterpret_cast<const uint4 *>(sn.desc) + doff + zl;
+                dsc_base = 0;
+                asm volatile("" : "+s"(dsc_base));
 #pragma unroll
                 for (int b = 0; b < kDescAhead && b < NB; ++b)
                     load_block(b);
@@ -709,9 +709,8 @@ integrate_strat_kernel(StratNetwork sn, DevOptions o, ZoneArgs za, const double 
                                             slot_phase(BoolTag<false>{});
                                         // descriptors of the first blocks of the next step
                                         {
-                                            int doff = 0;
-                                            asm volatile("" : "+s"(doff));
-                                            dsc = reinterpret_cast<const uint4 *>(sn.desc) + doff + zl;
+                                            dsc_base = 0;
+                                            asm volatile("" : "+s"(dsc_base));
 #pragma unroll
                                             for (int b = 0; b < kDescAhead && b < NB; ++b)
                                                 load_block(b);
