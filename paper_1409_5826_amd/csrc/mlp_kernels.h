@@ -379,8 +379,24 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
             a[e] = row0 ? f32_to_bf16_bits(src[32 * kk + kg + e]) : (uint16_t)0;
         return pack_bf16x8(a);
     };
-    auto ld = [&](const uint16_t *base, int tile_frag) {
-        return *reinterpret_cast<const uint4 *>(base + ((size_t)tile_frag * 64 + lane) * 8);
+    // weights and biases through buffer resources: the lane's offset is one register and a
+    // fragment's offset a scalar (the wave index is uniform), so no 64-bit address per load
+    // is computed, kept or spilled, and a tile's loads issue together
+    auto rsrc = [](const void *p, int bytes) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+    };
+    const __amdgpu_buffer_rsrc_t rw1 = rsrc(w.w1s, 8 * 6 * 64 * 16);
+    const __amdgpu_buffer_rsrc_t rw2 = rsrc(w.w2s, 8 * 4 * 64 * 16);
+    const __amdgpu_buffer_rsrc_t rw3 = rsrc(w.w3s, 4 * 64 * 16);
+    const __amdgpu_buffer_rsrc_t rb1 = rsrc(w.b1, kMlpHid * 4);
+    const __amdgpu_buffer_rsrc_t rb2 = rsrc(w.b2, kMlpHid * 4);
+    auto ld = [&](__amdgpu_buffer_rsrc_t r, int tile_frag) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16, tile_frag * 1024, 0);
+        return uint4{v[0], v[1], v[2], v[3]};
+    };
+    // bias of column 16 tn + lane (lanes 0..15)
+    auto bias = [&](__amdgpu_buffer_rsrc_t r, int tn) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, lane * 4, tn * 64, 0));
     };
     // layer 1
     {
@@ -391,7 +407,7 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
         uint4 nb[6];
 #pragma unroll
         for (int kk = 0; kk < 6; ++kk)
-            nb[kk] = ld(w.w1s, wave * 6 + kk);
+            nb[kk] = ld(rw1, wave * 6 + kk);
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
             const int tn = wave + t * W;
@@ -402,7 +418,7 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
             if (t + 1 < TPW) {
 #pragma unroll
                 for (int kk = 0; kk < 6; ++kk)
-                    nb[kk] = ld(w.w1s, (tn + W) * 6 + kk);
+                    nb[kk] = ld(rw1, (tn + W) * 6 + kk);
             }
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -411,7 +427,7 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
                                                               acc, 0, 0, 0);
             // row 0 of the tile sits in lanes 0..15, element 0
             if (lane < 16) {
-                const float v = acc[0] + w.b1[16 * tn + lane];
+                const float v = acc[0] + bias(rb1, tn);
                 h1[16 * tn + lane] = bf16_bits_to_f32(f32_to_bf16_bits(v > 0.0f ? v : 0.0f));
             }
         }
@@ -426,7 +442,7 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
         uint4 nb[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
-            nb[kk] = ld(w.w2s, wave * 4 + kk);
+            nb[kk] = ld(rw2, wave * 4 + kk);
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
             const int tn = wave + t * W;
@@ -437,7 +453,7 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
             if (t + 1 < TPW) {
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk)
-                    nb[kk] = ld(w.w2s, (tn + W) * 4 + kk);
+                    nb[kk] = ld(rw2, (tn + W) * 4 + kk);
             }
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -445,7 +461,7 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kk], __builtin_bit_cast(bf16x8, cb[kk]),
                                                               acc, 0, 0, 0);
             if (lane < 16) {
-                const float v = acc[0] + w.b2[16 * tn + lane];
+                const float v = acc[0] + bias(rb2, tn);
                 h2[16 * tn + lane] = bf16_bits_to_f32(f32_to_bf16_bits(v > 0.0f ? v : 0.0f));
             }
         }
@@ -456,7 +472,7 @@ __device__ inline float mlp_infer_group(const MlpDevice &w, const float *x, floa
         uint4 b3w[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
-            b3w[kk] = ld(w.w3s, kk);
+            b3w[kk] = ld(rw3, kk);
         f32x4 acc3 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
