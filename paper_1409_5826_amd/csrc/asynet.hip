@@ -125,6 +125,7 @@ struct asy_mlp {
           *g_a2 = nullptr, *g_a1 = nullptr;
     float *colsum = nullptr;  // [kColsumBlocks][4][128] partial column sums
     int64_t t = 0;  // Adam steps taken
+    bool bf16_current = false;  // W1b, W2b, W3b hold the masters' BF16 copies
 };
 
 namespace {
@@ -991,8 +992,11 @@ int mlp_pad(int n) { return (n + 31) / 32 * 32; }
 hipError_t mlp_forward_pass(asy_mlp *m, int n, const float *x, hipStream_t s)
 {
     const int B = mlp_pad(n);
-    hipLaunchKernelGGL(mlp_cast_weights_kernel, dim3(64), dim3(256), 0, s, m->p, m->W1b, m->W2b,
-                       m->W3b);
+    if (!m->bf16_current) {  // after new parameters; a training step's Adam keeps them current
+        hipLaunchKernelGGL(mlp_cast_weights_kernel, dim3(64), dim3(256), 0, s, m->p, m->W1b, m->W2b,
+                           m->W3b);
+        m->bf16_current = true;
+    }
     hipLaunchKernelGGL(mlp_pack_input_kernel, dim3(64), dim3(256), 0, s, n, B, x, m->xb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -1010,8 +1014,10 @@ hipError_t mlp_forward_pass(asy_mlp *m, int n, const float *x, hipStream_t s)
 }
 
 // Forward, loss and gradient into m->g.
+// With sums_in_adam the gradients of b1, b2, W3 and b3 are left in the column-sum partials
+// (m->colsum) for the Adam kernel, which adds them itself.
 hipError_t mlp_gradient_pass(asy_mlp *m, int n, const float *x, const float *y, float *loss,
-                             hipStream_t s)
+                             hipStream_t s, bool sums_in_adam = false)
 {
     const int B = mlp_pad(n);
     hipError_t e = mlp_forward_pass(m, n, x, s);
@@ -1043,8 +1049,9 @@ hipError_t mlp_gradient_pass(asy_mlp *m, int n, const float *x, const float *y, 
     const int rows_per = (B + kColsumBlocks - 1) / kColsumBlocks;
     hipLaunchKernelGGL(mlp_colsum_part_kernel, dim3(kColsumBlocks), dim3(kColsumGroups * kMlpHid),
                        0, s, B, rows_per, m->g_a1, m->g_a2, m->g_o, m->h2b, m->g_ob, m->colsum);
-    hipLaunchKernelGGL(mlp_colsum_final_kernel, dim3(1), dim3(kMlpHid), 0, s, kColsumBlocks,
-                       m->colsum, m->g);
+    if (!sums_in_adam)
+        hipLaunchKernelGGL(mlp_colsum_final_kernel, dim3(1), dim3(kMlpHid), 0, s, kColsumBlocks,
+                           m->colsum, m->g);
     return hipGetLastError();
 }
 
@@ -1879,6 +1886,7 @@ asy_status asy_mlp_set_params(asy_mlp *m, const float *params)
     HIP_TRY(hipMemset(m->m, 0, kMlpParams * 4));
     HIP_TRY(hipMemset(m->v, 0, kMlpParams * 4));
     m->t = 0;
+    m->bf16_current = false;
     return ASY_OK;
 }
 
@@ -1932,13 +1940,14 @@ asy_status asy_mlp_train_step(asy_mlp *m, int32_t n, const float *x, const float
     if (!y || !(lr > 0.0f) || !std::isfinite(lr))
         return fail(ASY_EINVAL, "y must be non-NULL and lr finite and > 0");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(mlp_gradient_pass(m, n, x, y, loss, s));
+    HIP_TRY(mlp_gradient_pass(m, n, x, y, loss, s, true));
     m->t += 1;
     const double beta1 = 0.9, beta2 = 0.999;
     const float c1 = (float)(1.0 - std::pow(beta1, (double)m->t));
     const float c2 = (float)(1.0 - std::pow(beta2, (double)m->t));
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->m, m->v, lr,
-                       (float)beta1, (float)beta2, 1e-8f, c1, c2);
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->colsum,
+                       kColsumBlocks, m->m, m->v, m->W1b, m->W2b, m->W3b, lr, (float)beta1,
+                       (float)beta2, 1e-8f, c1, c2);
     HIP_TRY(hipGetLastError());
     return ASY_OK;
 }
@@ -1959,12 +1968,13 @@ asy_status asy_mlp_train_epoch(asy_mlp *m, int32_t n_batches, int32_t batch, con
     for (int32_t b = 0; b < n_batches; ++b) {
         const size_t first = (size_t)b * (size_t)batch;
         HIP_TRY(mlp_gradient_pass(m, batch, x + first * kMlpIn, y + first,
-                                  losses ? losses + b : nullptr, s));
+                                  losses ? losses + b : nullptr, s, true));
         m->t += 1;
         const float c1 = (float)(1.0 - std::pow(beta1, (double)m->t));
         const float c2 = (float)(1.0 - std::pow(beta2, (double)m->t));
-        hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->m, m->v, lr,
-                           (float)beta1, (float)beta2, 1e-8f, c1, c2);
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->colsum,
+                           kColsumBlocks, m->m, m->v, m->W1b, m->W2b, m->W3b, lr, (float)beta1,
+                           (float)beta2, 1e-8f, c1, c2);
         HIP_TRY(hipGetLastError());
     }
     return ASY_OK;

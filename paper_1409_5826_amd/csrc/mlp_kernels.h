@@ -324,17 +324,50 @@ mlp_colsum_final_kernel(int blocks, const float *part, float *grad)
         grad[kOffB3] = t4;
 }
 
-// Adam on the FP32 masters; c1 = 1 - beta1^t, c2 = 1 - beta2^t
-__global__ void mlp_adam_kernel(float *p, const float *g, float *m, float *v, float lr, float beta1,
-                                float beta2, float eps, float c1, float c2)
+// Adam on the FP32 masters; c1 = 1 - beta1^t, c2 = 1 - beta2^t.  The gradients of b1, b2, W3 and
+// b3 come straight from the column-sum partials part[blocks][4][128], added in workgroup order as
+// mlp_colsum_final_kernel adds them (the same values), and every updated weight is written to its
+// BF16 copy as mlp_cast_weights_kernel writes it (W1b, W2b, column 0 of W3b), so a training step
+// needs neither of those two kernels.
+__global__ void mlp_adam_kernel(float *p, const float *g, const float *part, int blocks, float *m,
+                                float *v, uint16_t *W1b, uint16_t *W2b, uint16_t *W3b, float lr,
+                                float beta1, float beta2, float eps, float c1, float c2)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kMlpParams; i += gridDim.x * blockDim.x) {
-        const float gi = g[i];
+        // which column sum holds this parameter's gradient (-1: g holds it)
+        int sum = -1, j = 0;
+        if (i >= kOffB1 && i < kOffB1 + kMlpHid) {
+            sum = 0;
+            j = i - kOffB1;
+        } else if (i >= kOffB2 && i < kOffB2 + kMlpHid) {
+            sum = 1;
+            j = i - kOffB2;
+        } else if (i >= kOffW3 && i < kOffW3 + kMlpHid) {
+            sum = 2;
+            j = i - kOffW3;
+        } else if (i == kOffB3) {
+            sum = 3;
+        }
+        float gi;
+        if (sum >= 0) {
+            gi = 0.0f;
+            for (int q = 0; q < blocks; ++q)
+                gi += part[(size_t)q * 4 * kMlpHid + sum * kMlpHid + j];
+        } else {
+            gi = g[i];
+        }
         const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
         const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        const float pn = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pn;
+        if (i < kOffB1)
+            W1b[i - kOffW1] = f32_to_bf16_bits(pn);
+        else if (i >= kOffW2 && i < kOffB2)
+            W2b[i - kOffW2] = f32_to_bf16_bits(pn);
+        else if (sum == 2)
+            W3b[j * 16] = f32_to_bf16_bits(pn);
     }
 }
 
