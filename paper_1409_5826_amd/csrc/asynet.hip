@@ -1945,9 +1945,10 @@ asy_status asy_mlp_train_step(asy_mlp *m, int32_t n, const float *x, const float
     const double beta1 = 0.9, beta2 = 0.999;
     const float c1 = (float)(1.0 - std::pow(beta1, (double)m->t));
     const float c2 = (float)(1.0 - std::pow(beta2, (double)m->t));
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->colsum,
-                       kColsumBlocks, m->m, m->v, m->W1b, m->W2b, m->W3b, lr, (float)beta1,
-                       (float)beta2, 1e-8f, c1, c2);
+    // one thread per parameter
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, m->p, m->g,
+                       m->colsum, kColsumBlocks, m->m, m->v, m->W1b, m->W2b, m->W3b, lr,
+                       (float)beta1, (float)beta2, 1e-8f, c1, c2);
     HIP_TRY(hipGetLastError());
     return ASY_OK;
 }
@@ -1972,9 +1973,9 @@ asy_status asy_mlp_train_epoch(asy_mlp *m, int32_t n_batches, int32_t batch, con
         m->t += 1;
         const float c1 = (float)(1.0 - std::pow(beta1, (double)m->t));
         const float c2 = (float)(1.0 - std::pow(beta2, (double)m->t));
-        hipLaunchKernelGGL(mlp_adam_kernel, dim3(64), dim3(256), 0, s, m->p, m->g, m->colsum,
-                           kColsumBlocks, m->m, m->v, m->W1b, m->W2b, m->W3b, lr, (float)beta1,
-                           (float)beta2, 1e-8f, c1, c2);
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, m->p,
+                           m->g, m->colsum, kColsumBlocks, m->m, m->v, m->W1b, m->W2b, m->W3b, lr,
+                           (float)beta1, (float)beta2, 1e-8f, c1, c2);
         HIP_TRY(hipGetLastError());
     }
     return ASY_OK;
