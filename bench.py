@@ -346,6 +346,8 @@ def main(argv=None):
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposer comparison")
     ap.add_argument("--learned-zones", type=int, default=4096)
+    ap.add_argument("--learned-step-probe", action="store_true",
+                    help="time learned against plain zone-steps with a fixed network and exit")
     ap.add_argument("--mlp-train-probe", type=int, default=0,
                     help="only time this many epochs of MLP training (batch 1024) on 64 seeded "
                          "synthetic batches, for profiling the training kernels")
@@ -375,6 +377,9 @@ def main(argv=None):
         return 0
     if args.mlp_train_probe:
         print(json.dumps(mlp_train_probe(args.mlp_train_probe)), flush=True)
+        return 0
+    if args.learned_step_probe:
+        print(json.dumps(learned_step_probe()), flush=True)
         return 0
     lds_measured = {w: binding.asy_probe_lds_bandwidth(w) / 1e9 for w in (8, 16)}
     peak = max(LDS_PEAK_GBS, *lds_measured.values())
@@ -447,6 +452,34 @@ def main(argv=None):
         log("cpu baseline done")
     print(json.dumps(out), flush=True)
     return 0
+
+
+def learned_step_probe() -> dict:
+    """Device cost of a learned zone-step against a plain one: 1024 zones of the 150-species
+    constant-rate distribution (seed offset 1003) at tol 1e-2; the learned controller is driven
+    by a fixed seeded network (untrained: its proposals are poor, so every zone runs to the
+    200,000-attempt budget, which makes the count of attempted steps exact), each form timed as
+    the median of 2 launches (HIP events on the launch stream)."""
+    from paper_1409_5826_amd import binding, learned, workloads
+
+    wl = workloads.preset("n150_r1604_const", n_zones=1024, seed_offset=1003)
+    net = binding.Network(wl.network)
+    mlp = binding.Mlp(1024)
+    try:
+        mlp.set_params(learned.initial_params(4005))
+        net.set_mlp(mlp)
+        rl = learned.integrate(net, wl.zones, 1e-2, True, repeats=2, max_steps=200_000)
+        rp = learned.integrate(net, wl.zones, 1e-2, False, repeats=2)
+    finally:
+        mlp.close()
+        net.close()
+    att_l = int(rl.n_acc.sum() + rl.n_rej.sum())
+    att_p = int(rp.n_acc.sum() + rp.n_rej.sum())
+    return {"zones": 1024, "tol": 1e-2,
+            "learned_ms": rl.ms, "learned_attempted_zone_steps": att_l,
+            "learned_ns_per_zone_step": rl.ms * 1e6 / att_l,
+            "plain_ms": rp.ms, "plain_attempted_zone_steps": att_p,
+            "plain_ns_per_zone_step": rp.ms * 1e6 / att_p}
 
 
 def mlp_train_probe(epochs: int) -> dict:
